@@ -1,0 +1,22 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+    config.addinivalue_line("markers", "slow: longer CPU physics checks")
+
+
+@pytest.fixture(scope="session", autouse=True)
+def _oracle_built():
+    from oracle import build as ob
+    src = os.path.join(ROOT, "oracle", "lbm3_oracle.c")
+    if (not os.path.exists(ob.LIB)) or os.path.getmtime(ob.LIB) < os.path.getmtime(src):
+        ob.build()
+    yield
