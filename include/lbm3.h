@@ -1,0 +1,170 @@
+/*
+ * lbm3.h -- C ABI of the MI355X (gfx950) library for the per-timestep update
+ * of the ternary high-density-ratio free-energy lattice Boltzmann model with
+ * wetting walls (Bala, Pepona, Karlin, Kusumaatmaja, Semprebon,
+ * arXiv:1904.06881).
+ *
+ * One step (Sec. II C and Sec. IV of the paper):
+ *   moments rho, phi from the two population sets (density f: entropic
+ *   ELBM; phase field g: LBGK) -> ghost layers of the walls (force method
+ *   copy, or geometric interpolation / extrapolation toward the prescribed
+ *   contact angle) -> isotropic gradient and Laplacian stencils -> chemical
+ *   potentials and pressure tensor of the free energy -> interfacial force
+ *   F = div(rho c_s^2 I - P) -> entropic collision with exact-difference
+ *   forcing for f, LBGK for g -> streaming with halfway bounce-back.
+ *
+ * Conventions shared by every entry point
+ *   - Lattice D2Q9 (2D) or D3Q27 (3D); velocities are {-1,0,1}^D in
+ *     lexicographic order, x component most significant: population index
+ *     i = sum_a (c_ia + 1) 3^(D-1-a); rest population (Q-1)/2; opposite
+ *     Q-1-i.  Weights are products of 2/3 (c = 0) and 1/6 (c = +-1).
+ *   - Grid n[0] x n[1] x n[2] (n[2] = 1 in 2D), node index
+ *     x + n[0] (y + n[1] z).  Host arrays of fields are FP64 in that order;
+ *     host arrays of populations are FP64 [Q][N].
+ *   - Walls (walls = 1) sit on the last axis (y in 2D, z in 3D): indices 0
+ *     and n-1 of that axis are ghost (solid) layers holding rho and phi only,
+ *     the wall planes are half way to the first fluid layer.  Every other
+ *     axis is periodic.  walls = 0: fully periodic.
+ *   - Components follow the paper: 1 gas, 2 and 3 liquids, phi = chi (C2-C3).
+ *   - Device memory: the caller allocates one workspace of lbm3_footprint()
+ *     bytes (e.g. a PyTorch uint8 tensor) and owns it; the handle only
+ *     sub-allocates from it and never calls the device allocator.  All
+ *     device work is enqueued on the caller's HIP stream.
+ *   - Errors: every call returns an lbm3_status; no exception crosses the
+ *     ABI; lbm3_last_error() gives a message for the last failure on a
+ *     handle (or of the last failed create when passed NULL).
+ *   - Threading: one handle per stream; calls on one handle must not overlap.
+ */
+#ifndef LBM3_H
+#define LBM3_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm3 lbm3;
+
+typedef enum {
+    LBM3_OK = 0,
+    LBM3_EINVAL = -1,    /* bad shape or parameter */
+    LBM3_ENOMEM = -2,    /* workspace smaller than lbm3_footprint() */
+    LBM3_EUNSTABLE = -3, /* observe found NaN / rho <= 0 */
+    LBM3_EDEVICE = -4,   /* HIP runtime error */
+    LBM3_ESTATE = -5,    /* e.g. step before init */
+    LBM3_ECALIB = -6     /* (gamma, width) -> (lambda, kappa) map failed */
+} lbm3_status;
+
+enum { LBM3_D2Q9 = 9, LBM3_D3Q27 = 27 };
+enum { LBM3_WET_FORCE = 0, LBM3_WET_GEOM_INTERP = 1, LBM3_WET_GEOM_EXTRAP = 2 };
+enum { LBM3_FP64 = 0, LBM3_FP32 = 1, LBM3_FP16S = 2 };
+enum {
+    LBM3_NO_COLLIDE = 1u,   /* streaming and bounce-back only */
+    LBM3_FORCE_ALPHA2 = 2u  /* alpha = 2 everywhere (BGK with 1/tau_f = 2 beta) */
+};
+
+/* Problem statement (paper Sec. II-IV).  Zero-initialise, then set. */
+typedef struct {
+    int32_t lattice;        /* LBM3_D2Q9 or LBM3_D3Q27 */
+    int32_t n[3];           /* nx, ny, nz (nz = 1 for D2Q9); >= 3 on the wall axis */
+    int32_t walls;          /* 1: walls at both ends of the last axis; 0: periodic */
+    double  rho_l, rho_g;   /* coexistence densities (Carnahan-Starling, Sec. II A):
+                               the temperature follows from rho_l/rho_g at the
+                               paper's a/b = 0.185, rescaled to this rho_l */
+    int32_t native;         /* 1: use lambda/kappa; 0: derive them from the
+                               tensions and the interface width */
+    double  lambda[3], kappa[3];            /* free energy, Eqs. 2-3 */
+    double  gamma12, gamma13, gamma23;      /* target tensions (native = 0) */
+    double  width;          /* 10-90 % interface width, 4 alpha23 (native = 0) */
+    double  chi;            /* phi scale (paper: 5) */
+    double  tau_f;          /* ELBM: beta = 1/(2 tau_f), nu = (tau_f - 1/2)/3 */
+    double  tau_g;          /* LBGK relaxation time of g */
+    double  Gamma;          /* mobility M = Gamma (tau_g - 1/2) */
+    int32_t wetting;        /* LBM3_WET_* */
+    double  theta_deg[2][3];/* per wall (0: index 0, 1: index n-1): theta21,
+                               theta31, theta23, degrees, measured in the
+                               liquid (liquid 2 at the 2-3 interface), Sec. IV */
+    double  kw[2][2];       /* per wall: kappa_rho^w, kappa_phi^w (force method) */
+    int32_t precision;      /* LBM3_FP64, LBM3_FP32, LBM3_FP16S (FP32 arithmetic,
+                               populations stored in FP16 as density-scaled
+                               offsets from the lattice weights) */
+    uint32_t flags;         /* LBM3_NO_COLLIDE | LBM3_FORCE_ALPHA2 */
+    double  alpha_eps;      /* alpha = 2 below this deviation (0: 1e-3) */
+    double  alpha_tol;      /* Newton tolerance (0: 1e-10 FP64, 1e-5 FP32) */
+    int32_t alpha_maxit;    /* Newton iteration cap (0: 20) */
+} lbm3_params;
+
+/* Values the library derives from lbm3_params (lbm3_resolve). */
+typedef struct {
+    double a, b, T, C, psi0;   /* Carnahan-Starling constants, R = 1 */
+    double rho_l, rho_g;
+    double lambda[3], kappa[3];
+    double kappa_rr, kappa_pp, kappa_x;   /* gradient mixing coefficients */
+    double beta, cot_theta[2][3];
+} lbm3_derived;
+
+/* Observables of the current state (sums over fluid nodes, FP64). */
+typedef struct {
+    double  mass[3];        /* sum of C1, C2, C3 */
+    double  rho_sum, phi_sum;
+    double  mom[3];         /* sum of rho u (bare velocity) */
+    double  kinetic;        /* sum of rho |u|^2 / 2 */
+    double  umax;           /* max |u| */
+    int64_t n_bad;          /* nodes with rho <= 0 or non-finite fields */
+    int64_t n_newton, n_shortcut, n_fallback; /* entropic alpha kinds since init */
+    int64_t step;
+} lbm3_obs;
+
+enum { LBM3_OBS_SUMS = 1u, LBM3_OBS_FIELDS = 2u, LBM3_OBS_POPS = 4u };
+
+/* Bytes of device workspace a handle with these parameters needs; 0 when
+ * the parameters are invalid. */
+size_t lbm3_footprint(const lbm3_params *p);
+
+/* Derive the thermodynamic constants and (native = 0) lambda, kappa from the
+ * tensions and width.  Host only.  LBM3_EINVAL / LBM3_ECALIB on failure. */
+lbm3_status lbm3_resolve(const lbm3_params *p, lbm3_derived *out);
+
+/* Create a handle.  dev_workspace: device pointer to >= lbm3_footprint(p)
+ * bytes, 256-byte aligned, owned by the caller and kept alive until
+ * lbm3_destroy; hip_stream: a hipStream_t (NULL = default stream).  The
+ * parameters are copied. */
+lbm3_status lbm3_create(const lbm3_params *p, void *dev_workspace, size_t bytes,
+                        void *hip_stream, lbm3 **out);
+
+/* Initial state from host FP64 fields of the full grid (ghost entries are
+ * ignored): f = f^eq(rho0, 0) = w rho0; g = g^eq(phi0, mu_phi, 0) with
+ * mu_phi from the ghost fill and stencils of the initial fields.  Copies the
+ * arrays and returns after the upload has been enqueued and completed. */
+lbm3_status lbm3_init(lbm3 *h, const double *rho0, const double *phi0);
+
+/* Enqueue nsteps full updates on the handle's stream (asynchronous). */
+lbm3_status lbm3_step(lbm3 *h, int64_t nsteps);
+
+/* Synchronise the stream and report the current state.  what: LBM3_OBS_*
+ * bits.  out may be NULL unless LBM3_OBS_SUMS is set.  rho_out/phi_out
+ * (N doubles, full grid, ghost layers as last filled) with LBM3_OBS_FIELDS;
+ * f_out/g_out (Q*N doubles, [Q][N]) with LBM3_OBS_POPS.  Returns
+ * LBM3_EUNSTABLE when the sums found NaN or rho <= 0. */
+lbm3_status lbm3_observe(lbm3 *h, uint32_t what, lbm3_obs *out, double *rho_out,
+                         double *phi_out, double *f_out, double *g_out);
+
+/* Contact angle of the concentration C_k (k = 2 or 3) against wall w (0 or
+ * 1): FP64 least-squares circle (2D) / sphere (3D) through the C_k = 1/2
+ * iso-points on grid lines more than `exclude` lattice units from the wall
+ * plane; theta = arccos(-h/R) with h the centre height over the wall plane
+ * measured into the fluid.  out[0] = theta (degrees), out[1..3] = centre
+ * (x, y[, z]) , out[4] = radius, out[5] = number of points.  Synchronises the
+ * stream. */
+lbm3_status lbm3_contact_angle(lbm3 *h, int32_t comp, int32_t wall, double exclude,
+                               double *out);
+
+lbm3_status lbm3_destroy(lbm3 *h);
+const char *lbm3_last_error(const lbm3 *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM3_H */

@@ -310,14 +310,18 @@ void or_local_thermo(const or_params *p, double rho, double phi,
 /* Entropic alpha: non-trivial root of H(f' + alpha Delta) = H(f') with
  * H(f) = sum f ln(f/w) (Eqs. 30-32), Delta = f^eq(rho, u + du) - f'.
  * Writing x_i = Delta_i / f'_i and using that ln(f^eq_i / w_i) is linear in
- * c_i while Delta carries no mass or momentum, the equation is
- *   G(alpha) = sum_i [(f'_i + alpha Delta_i) log1p(alpha x_i)
- *                     - alpha Delta_i log1p(x_i)] = 0,
- *   G'(alpha) = sum_i Delta_i [log1p(alpha x_i) - log1p(x_i)].
+ * c_i while Delta carries no mass and no momentum (sum Delta = sum Delta c = 0),
+ * the equation is G(alpha) = 0 with
+ *   G(alpha) = sum_i f'_i [(1 + alpha x_i) log1p(alpha x_i)
+ *                          - alpha x_i (1 + log1p(x_i))],
+ *   G'(alpha) = sum_i f'_i x_i [log1p(alpha x_i) - log1p(x_i)].
+ * (The term alpha sum Delta, zero by conservation, is left out: kept, its
+ * rounding alone would move the root by ~1e-16 / x^2.)
  * reading (the paper gives only the equation):
  *   - a non-positive mirror population: alpha = 2 (fallback);
- *   - max |x_i| < eps: alpha = 2 (shortcut; the root is 2 to leading order
- *     and ill-conditioned there);
+ *   - max |x_i| < eps: the small-deviation root from expanding G about
+ *     alpha = 2, alpha = 2 + (S3 - 2 S4) / (3 S2 - 4 S3), S_k = sum f' x^k
+ *     (alpha = 2 when S2 = 0);
  *   - otherwise Newton from min(2, (1 + alpha_max)/2), alpha_max =
  *     min_{Delta_i<0} -f'_i/Delta_i the positivity limit; an iterate that
  *     leaves (1, alpha_max) is replaced by the midpoint towards the violated
@@ -336,7 +340,18 @@ int or_alpha(int Q, const double *w, const double *fp, const double *delta,
         x[i] = delta[i] / fp[i];
         if (fabs(x[i]) > xmax) xmax = fabs(x[i]);
     }
-    if (xmax < eps) { *alpha = 2.0; return 0; }
+    if (xmax < eps) {
+        double S2 = 0, S3 = 0, S4 = 0;
+        for (int i = 0; i < Q; ++i) {
+            double x2 = x[i] * x[i];
+            S2 += fp[i] * x2;
+            S3 += fp[i] * x2 * x[i];
+            S4 += fp[i] * x2 * x2;
+        }
+        double den = 3.0 * S2 - 4.0 * S3;
+        *alpha = (den > 0.0) ? 2.0 + (S3 - 2.0 * S4) / den : 2.0;
+        return 0;
+    }
     double amax = INFINITY;
     for (int i = 0; i < Q; ++i)
         if (delta[i] < 0.0 && -fp[i] / delta[i] < amax) amax = -fp[i] / delta[i];
@@ -346,8 +361,8 @@ int or_alpha(int Q, const double *w, const double *fp, const double *delta,
         double G = 0.0, dG = 0.0;
         for (int i = 0; i < Q; ++i) {
             double la = log1p(a * x[i]);
-            G += (fp[i] + a * delta[i]) * la - a * delta[i] * l1x[i];
-            dG += delta[i] * (la - l1x[i]);
+            G += fp[i] * ((1.0 + a * x[i]) * la - a * x[i] * (1.0 + l1x[i]));
+            dG += fp[i] * x[i] * (la - l1x[i]);
         }
         if (!(dG > 0.0)) break;
         double an = a - G / dG;
@@ -892,6 +907,7 @@ int or_init(or_state *s, const double *rho0, const double *phi0)
     s->step = 0;
     s->n_newton = s->n_shortcut = s->n_fallback = 0;
     pass_moments(s);
+    pass_ghost(s);
     return 0;
 }
 
@@ -917,7 +933,9 @@ int or_step(or_state *s, int64_t nsteps)
         pass_stream(s);
         s->step++;
     }
+    /* moments and ghost layers of the state reached (reported by or_get) */
     pass_moments(s);
+    pass_ghost(s);
     return 0;
 }
 
@@ -1024,34 +1042,28 @@ double or_flat_tension(const or_params *p, int pair, int n, double *width,
     double stiffp = (fabs(p->lambda[1]) + fabs(p->lambda[2])) / (p->chi * p->chi) +
                     4.0 * (fabs(k.kpp) + fabs(k.kx));
     double dt = 0.4 / (stiff > stiffp ? stiff : stiffp);
-    double gprev = 0.0;
-    for (int it = 0; it < 4000000; ++it) {
-        if (it % 2000 == 0) {
-            /* stop once the tension has converged (the interface position is a
-             * neutral mode and keeps drifting very slowly) */
-            double gnow = 0.0;
-            for (int x = 1; x < n - 1; ++x) {
-                double dr = 0.5 * (r[x + 1] - r[x - 1]), dp = 0.5 * (ph[x + 1] - ph[x - 1]);
-                gnow += k.krr * dr * dr + k.kpp * dp * dp + 2.0 * k.kx * dr * dp;
-            }
-            if (it > 0 && fabs(gnow - gprev) < 1e-8 * fabs(gnow)) break;
-            gprev = gnow;
-        }
+    /* reading: the interface position is a neutral mode of the flat
+     * problem; it is pinned by holding the field that changes across it (rho
+     * for the liquid-gas pairs, phi for 2-3) at the centre node at the mean of
+     * its two bulk values */
+    const int pin = n / 2;
+    const int pin_phi = (pair == 23);
+    if (pin_phi) ph[pin] = 0.5 * (pA + pB); else r[pin] = 0.5 * (rA + rB);
+    for (int it = 0; it < 20000000; ++it) {
         double res = 0.0;
         for (int x = 1; x < n - 1; ++x) {
             double Lr = r[x + 1] + r[x - 1] - 2.0 * r[x];
             double Lp = ph[x + 1] + ph[x - 1] - 2.0 * ph[x];
             double mrb, mpb, fb;
             bulk_terms(p, r[x], ph[x], &mrb, &mpb, &fb);
-            mr[x] = mrb - k.krr * Lr - k.kx * Lp;
-            mp[x] = mpb - k.kpp * Lp - k.kx * Lr;
+            mr[x] = (x == pin && !pin_phi) ? 0.0 : mrb - k.krr * Lr - k.kx * Lp;
+            mp[x] = (x == pin && pin_phi) ? 0.0 : mpb - k.kpp * Lp - k.kx * Lr;
             double e = fabs(mr[x]) + fabs(mp[x]);
             if (e > res) res = e;
         }
         for (int x = 1; x < n - 1; ++x) {
             r[x] -= dt * mr[x];
             ph[x] -= dt * mp[x];
-            if (r[x] < 0.5 * p->rho_g) r[x] = 0.5 * p->rho_g;
         }
         if (res < 1e-13) break;
     }

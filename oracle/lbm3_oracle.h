@@ -111,7 +111,8 @@ int       or_init(or_state *s, const double *rho0, const double *phi0);
 /* Set populations directly (Q*N each); used by the streaming pins. */
 int       or_set_pops(or_state *s, const double *f, const double *g);
 int       or_step(or_state *s, int64_t nsteps);
-/* Copies of the state: rho/phi on the full grid (ghost layers as last filled),
+/* Copies of the state: rho/phi on the full grid (ghost layers of the current
+ * fields),
  * f/g populations (Q*N).  Any pointer may be NULL. */
 void      or_get(const or_state *s, double *rho, double *phi, double *f,
                  double *g);
@@ -125,9 +126,11 @@ int64_t   or_N(const or_state *s);
 
 /* --- calibration --------------------------------------------------------- */
 /* Flat interface between two bulk phases relaxed on a 1D lattice of n nodes
- * (spacing 1, fixed bulk values at both ends) by gradient flow of the free
- * energy; returns its surface tension, and the 10-90 % width of the
- * concentration `wcomp` (1..3) if width != NULL.  pair = 12, 13 or 23. */
+ * (spacing 1, fixed bulk values at both ends, interface pinned by holding
+ * rho (liquid-gas) or phi (2-3) at the centre node at its mean bulk value)
+ * by gradient flow of the
+ * free energy; returns its surface tension and, if width != NULL, the 10-90 %
+ * width of C1 (liquid-gas pairs) or C2 (pair 23).  pair = 12, 13 or 23. */
 double or_flat_tension(const or_params *p, int pair, int n, double *width,
                        double *rho_out, double *phi_out);
 

@@ -1,0 +1,413 @@
+// C ABI of the lbm3 library (declared in include/lbm3.h): parameter
+// resolution, workspace layout, and the host side of init / step / observe.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm3.h"
+#include "lbm3_internal.h"
+#include "lbm3_params.h"
+
+using lbm3k::Buffers;
+using lbm3k::KParams;
+
+struct lbm3 {
+    lbm3_params p;
+    lbm3_derived d;
+    KParams kp;
+    Buffers b;
+    int prec;
+    hipStream_t stream;
+    int pc, fc;            // current population buffer, fields it is encoded with
+    bool inited;
+    int64_t step;
+    std::string err;
+};
+
+static std::string g_create_err;
+
+namespace {
+
+const double PI = 3.14159265358979323846;
+
+struct Layout {
+    size_t f[2], g[2], rho[2], phi[2], scratch, counters, partials, result, total;
+};
+
+int lattice_D(int32_t lattice) { return lattice == LBM3_D2Q9 ? 2 : (lattice == LBM3_D3Q27 ? 3 : 0); }
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+bool validate(const lbm3_params *p, std::string &why)
+{
+    if (!p) { why = "null parameters"; return false; }
+    int D = lattice_D(p->lattice);
+    if (!D) { why = "lattice must be 9 (D2Q9) or 27 (D3Q27)"; return false; }
+    int nz = D == 2 ? 1 : p->n[2];
+    if (p->n[0] < 1 || p->n[1] < 1 || nz < 1) { why = "grid extents must be positive"; return false; }
+    if (D == 2 && p->n[2] > 1) { why = "n[2] must be 1 for D2Q9"; return false; }
+    int nw = D == 2 ? p->n[1] : nz;
+    if (p->walls && nw < 3) { why = "the wall axis needs at least 3 layers"; return false; }
+    if ((long long)p->n[0] * p->n[1] * nz > (1LL << 34)) { why = "grid too large"; return false; }
+    if (!(p->rho_l > 0.0) || !(p->rho_g > 0.0) || !(p->rho_l > p->rho_g)) {
+        why = "need rho_l > rho_g > 0";
+        return false;
+    }
+    if (!(p->chi > 0.0)) { why = "chi must be positive"; return false; }
+    if (!(p->tau_f > 0.5) || !(p->tau_g > 0.5)) { why = "relaxation times must exceed 1/2"; return false; }
+    if (p->wetting < 0 || p->wetting > 2) { why = "unknown wetting method"; return false; }
+    if (p->precision < 0 || p->precision > 2) { why = "unknown precision"; return false; }
+    if (p->walls && p->wetting != LBM3_WET_FORCE) {
+        for (int w = 0; w < 2; ++w)
+            for (int k = 0; k < 3; ++k) {
+                double t = p->theta_deg[w][k];
+                if (!(t > 0.0 && t < 180.0)) { why = "contact angles must lie in (0, 180)"; return false; }
+                double ct = std::cos(t * PI / 180.0) / std::sin(t * PI / 180.0);
+                if (std::fabs(ct) > 3.0 + 1e-9 && p->wetting == LBM3_WET_GEOM_INTERP) {
+                    why = "geometric interpolation supports |cot(theta)| <= 3 (theta in [18.43, 161.57] deg)";
+                    return false;
+                }
+            }
+    }
+    if (p->native == 0) {
+        if (!(p->gamma12 > 0 && p->gamma13 > 0 && p->gamma23 > 0 && p->width > 0)) {
+            why = "native = 0 needs positive gamma12, gamma13, gamma23 and width";
+            return false;
+        }
+    }
+    return true;
+}
+
+Layout layout(const lbm3_params *p)
+{
+    Layout L{};
+    int D = lattice_D(p->lattice);
+    int Q = D == 2 ? 9 : 27;
+    long long N = (long long)p->n[0] * p->n[1] * (D == 2 ? 1 : p->n[2]);
+    size_t s = p->precision == LBM3_FP64 ? 8 : (p->precision == LBM3_FP32 ? 4 : 2);
+    size_t r = p->precision == LBM3_FP64 ? 8 : 4;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
+    for (int k = 0; k < 2; ++k) L.f[k] = take((size_t)Q * N * s);
+    for (int k = 0; k < 2; ++k) L.g[k] = take((size_t)Q * N * s);
+    for (int k = 0; k < 2; ++k) L.rho[k] = take((size_t)N * r);
+    for (int k = 0; k < 2; ++k) L.phi[k] = take((size_t)N * r);
+    L.scratch = take((size_t)N * 8);
+    L.counters = take(8 * sizeof(unsigned long long));
+    L.partials = take((size_t)1024 * 16 * sizeof(double));
+    L.result = take(32 * sizeof(double));
+    L.total = off;
+    return L;
+}
+
+double cot_deg(double deg)
+{
+    double t = deg * PI / 180.0;
+    double c = std::cos(t) / std::sin(t);
+    double r = std::nearbyint(c);
+    if (std::fabs(c - r) < 1e-9) c = r;  // exact lattice copies at the special angles
+    return c;
+}
+
+lbm3_status set_err(lbm3 *h, lbm3_status st, const std::string &m)
+{
+    if (h) h->err = m;
+    else g_create_err = m;
+    return st;
+}
+
+lbm3_status hip_err(lbm3 *h, hipError_t e, const char *where)
+{
+    return set_err(h, LBM3_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm3_footprint(const lbm3_params *p)
+{
+    std::string why;
+    if (!validate(p, why)) return 0;
+    return layout(p).total;
+}
+
+lbm3_status lbm3_resolve(const lbm3_params *p, lbm3_derived *out)
+{
+    std::string why;
+    if (!out || !validate(p, why)) return LBM3_EINVAL;
+    lbm3_derived d{};
+    if (!lbm3h::coexistence(p->rho_l / p->rho_g, p->rho_l, d.a, d.b, d.T, d.C, d.psi0, d.rho_l, d.rho_g))
+        return LBM3_EINVAL;
+    if (p->native) {
+        for (int k = 0; k < 3; ++k) { d.lambda[k] = p->lambda[k]; d.kappa[k] = p->kappa[k]; }
+    } else {
+        if (lbm3h::calibrate(p->gamma12, p->gamma13, p->gamma23, p->width, d.rho_l, d.rho_g, p->chi, d.a,
+                             d.b, d.T, d.C, d.psi0, d.lambda, d.kappa) != 0)
+            return LBM3_ECALIB;
+    }
+    double drho = d.rho_l - d.rho_g;
+    d.kappa_rr = d.kappa[0] + (d.kappa[1] + d.kappa[2]) / (4.0 * drho * drho);
+    d.kappa_pp = (d.kappa[1] + d.kappa[2]) / (4.0 * p->chi * p->chi);
+    d.kappa_x = (d.kappa[1] - d.kappa[2]) / (4.0 * p->chi * drho);
+    d.beta = 1.0 / (2.0 * p->tau_f);
+    for (int w = 0; w < 2; ++w)
+        for (int k = 0; k < 3; ++k) d.cot_theta[w][k] = p->walls ? cot_deg(p->theta_deg[w][k]) : 0.0;
+    *out = d;
+    return LBM3_OK;
+}
+
+lbm3_status lbm3_create(const lbm3_params *p, void *ws, size_t bytes, void *stream, lbm3 **out)
+{
+    std::string why;
+    if (!out) return set_err(nullptr, LBM3_EINVAL, "null output handle");
+    *out = nullptr;
+    if (!validate(p, why)) return set_err(nullptr, LBM3_EINVAL, why);
+    Layout L = layout(p);
+    if (!ws || bytes < L.total) return set_err(nullptr, LBM3_ENOMEM, "workspace smaller than lbm3_footprint()");
+    if (((uintptr_t)ws & 255) != 0) return set_err(nullptr, LBM3_EINVAL, "workspace must be 256-byte aligned");
+    lbm3_derived d;
+    lbm3_status st = lbm3_resolve(p, &d);
+    if (st != LBM3_OK)
+        return set_err(nullptr, st, st == LBM3_ECALIB ? "tension calibration failed" : "no Carnahan-Starling coexistence for rho_l/rho_g");
+    lbm3 *h = new (std::nothrow) lbm3();
+    if (!h) return set_err(nullptr, LBM3_ENOMEM, "host allocation failed");
+    h->p = *p;
+    h->d = d;
+    h->prec = p->precision;
+    h->stream = (hipStream_t)stream;
+    int D = lattice_D(p->lattice);
+    KParams &k = h->kp;
+    k.D = D;
+    k.Q = D == 2 ? 9 : 27;
+    k.nx = p->n[0];
+    k.ny = p->n[1];
+    k.nz = D == 2 ? 1 : p->n[2];
+    k.nw = D == 2 ? k.ny : k.nz;
+    k.walls = p->walls ? 1 : 0;
+    k.N = (long long)k.nx * k.ny * k.nz;
+    k.PS = D == 2 ? k.nx : (long long)k.nx * k.ny;
+    k.rho_l = d.rho_l;
+    k.rho_g = d.rho_g;
+    k.drho = d.rho_l - d.rho_g;
+    k.chi = p->chi;
+    k.a = d.a; k.b = d.b; k.T = d.T; k.C = d.C; k.psi0 = d.psi0;
+    k.lam1 = d.lambda[0]; k.lam2 = d.lambda[1]; k.lam3 = d.lambda[2];
+    k.krr = d.kappa_rr; k.kpp = d.kappa_pp; k.kx = d.kappa_x;
+    k.beta = d.beta;
+    k.inv_tau_g = 1.0 / p->tau_g;
+    k.Gamma = p->Gamma;
+    k.wetting = p->wetting;
+    for (int w = 0; w < 2; ++w) {
+        for (int c = 0; c < 3; ++c) k.cot[w][c] = d.cot_theta[w][c];
+        for (int c = 0; c < 2; ++c) k.kw[w][c] = p->kw[w][c];
+    }
+    k.alpha_eps = p->alpha_eps > 0 ? p->alpha_eps : 1e-3;
+    k.alpha_tol = p->alpha_tol > 0 ? p->alpha_tol : (p->precision == LBM3_FP64 ? 1e-10 : 1e-5);
+    k.alpha_maxit = p->alpha_maxit > 0 ? p->alpha_maxit : 20;
+    k.flags = p->flags;
+    char *base = (char *)ws;
+    Buffers &b = h->b;
+    for (int i = 0; i < 2; ++i) {
+        b.f[i] = base + L.f[i];
+        b.g[i] = base + L.g[i];
+        b.rho[i] = base + L.rho[i];
+        b.phi[i] = base + L.phi[i];
+    }
+    b.scratch = (double *)(base + L.scratch);
+    b.counters = (unsigned long long *)(base + L.counters);
+    b.partials = (double *)(base + L.partials);
+    b.result = (double *)(base + L.result);
+    b.n_partials = 1024;
+    h->pc = h->fc = 0;
+    h->inited = false;
+    h->step = 0;
+    *out = h;
+    return LBM3_OK;
+}
+
+lbm3_status lbm3_init(lbm3 *h, const double *rho0, const double *phi0)
+{
+    if (!h) return LBM3_EINVAL;
+    if (!rho0 || !phi0) return set_err(h, LBM3_EINVAL, "null initial field");
+    const KParams &k = h->kp;
+    size_t bytes = (size_t)k.N * sizeof(double);
+    for (long long n = 0; n < k.N; ++n) {
+        long long p = k.D == 2 ? n / k.nx : n / ((long long)k.nx * k.ny);
+        bool fluid = !k.walls || (p >= 1 && p <= k.nw - 2);
+        if (fluid && !(rho0[n] > 0.0 && std::isfinite(rho0[n]) && std::isfinite(phi0[n])))
+            return set_err(h, LBM3_EINVAL, "initial rho must be positive and finite on fluid nodes");
+    }
+    hipError_t e;
+    const double *src[2] = {rho0, phi0};
+    for (int which = 0; which < 2; ++which) {
+        if ((e = hipMemcpyAsync(h->b.scratch, src[which], bytes, hipMemcpyHostToDevice, h->stream)) != hipSuccess)
+            return hip_err(h, e, "upload");
+        if (lbm3k::launch_init_field(k, h->prec, h->b, which, h->stream)) return set_err(h, LBM3_EDEVICE, "init launch failed");
+    }
+    if (lbm3k::launch_ghost(k, h->prec, h->b, 0, h->stream)) return set_err(h, LBM3_EDEVICE, "ghost launch failed");
+    if (lbm3k::launch_init(k, h->prec, h->b, h->stream)) return set_err(h, LBM3_EDEVICE, "init launch failed");
+    if ((e = hipMemsetAsync(h->b.counters, 0, 8 * sizeof(unsigned long long), h->stream)) != hipSuccess)
+        return hip_err(h, e, "counters");
+    if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return hip_err(h, e, "init");
+    h->pc = h->fc = 0;
+    h->step = 0;
+    h->inited = true;
+    return LBM3_OK;
+}
+
+lbm3_status lbm3_step(lbm3 *h, int64_t nsteps)
+{
+    if (!h) return LBM3_EINVAL;
+    if (!h->inited) return set_err(h, LBM3_ESTATE, "step before init");
+    if (nsteps < 0) return set_err(h, LBM3_EINVAL, "negative step count");
+    const KParams &k = h->kp;
+    for (int64_t t = 0; t < nsteps; ++t) {
+        if (lbm3k::launch_moments(k, h->prec, h->b, h->pc, h->fc, h->stream) ||
+            lbm3k::launch_ghost(k, h->prec, h->b, 1 - h->fc, h->stream) ||
+            lbm3k::launch_fused(k, h->prec, h->b, h->pc, h->fc, h->stream))
+            return set_err(h, LBM3_EDEVICE, "kernel launch failed");
+        h->pc ^= 1;
+        h->fc ^= 1;
+        h->step++;
+    }
+    return LBM3_OK;
+}
+
+lbm3_status lbm3_observe(lbm3 *h, uint32_t what, lbm3_obs *out, double *rho_out, double *phi_out, double *f_out,
+                         double *g_out)
+{
+    if (!h) return LBM3_EINVAL;
+    if (!h->inited) return set_err(h, LBM3_ESTATE, "observe before init");
+    const KParams &k = h->kp;
+    hipError_t e;
+    size_t bytes = (size_t)k.N * sizeof(double);
+    lbm3_status status = LBM3_OK;
+    if (what & LBM3_OBS_FIELDS) {
+        // moments and ghost layers of the current state into the spare fields
+        if (lbm3k::launch_moments(k, h->prec, h->b, h->pc, h->fc, h->stream) ||
+            lbm3k::launch_ghost(k, h->prec, h->b, 1 - h->fc, h->stream))
+            return set_err(h, LBM3_EDEVICE, "kernel launch failed");
+        double *dst[2] = {rho_out, phi_out};
+        for (int which = 0; which < 2; ++which) {
+            if (!dst[which]) continue;
+            if (lbm3k::launch_export_field(k, h->prec, h->b, 1 - h->fc, which, h->stream))
+                return set_err(h, LBM3_EDEVICE, "export launch failed");
+            if ((e = hipMemcpyAsync(dst[which], h->b.scratch, bytes, hipMemcpyDeviceToHost, h->stream)) != hipSuccess)
+                return hip_err(h, e, "download");
+            if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return hip_err(h, e, "download");
+        }
+    }
+    if (what & LBM3_OBS_POPS) {
+        double *dst[2] = {f_out, g_out};
+        for (int which = 0; which < 2; ++which) {
+            if (!dst[which]) continue;
+            for (int i = 0; i < k.Q; ++i) {
+                if (lbm3k::launch_export_pop(k, h->prec, h->b, h->pc, h->fc, which, i, h->stream))
+                    return set_err(h, LBM3_EDEVICE, "export launch failed");
+                if ((e = hipMemcpyAsync(dst[which] + (size_t)i * k.N, h->b.scratch, bytes, hipMemcpyDeviceToHost,
+                                        h->stream)) != hipSuccess)
+                    return hip_err(h, e, "download");
+                if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return hip_err(h, e, "download");
+            }
+        }
+    }
+    if (what & LBM3_OBS_SUMS) {
+        if (!out) return set_err(h, LBM3_EINVAL, "null observable output");
+        if (lbm3k::launch_observe(k, h->prec, h->b, h->pc, h->fc, h->stream))
+            return set_err(h, LBM3_EDEVICE, "observe launch failed");
+        double r[16];
+        unsigned long long c[4];
+        if ((e = hipMemcpyAsync(r, h->b.result, sizeof(r), hipMemcpyDeviceToHost, h->stream)) != hipSuccess ||
+            (e = hipMemcpyAsync(c, h->b.counters, sizeof(c), hipMemcpyDeviceToHost, h->stream)) != hipSuccess)
+            return hip_err(h, e, "observe download");
+        if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return hip_err(h, e, "observe");
+        for (int q = 0; q < 3; ++q) out->mass[q] = r[q];
+        out->rho_sum = r[3];
+        out->phi_sum = r[4];
+        for (int q = 0; q < 3; ++q) out->mom[q] = r[5 + q];
+        out->kinetic = r[8];
+        out->umax = r[9];
+        out->n_bad = (int64_t)r[12];
+        out->n_newton = (int64_t)c[0];
+        out->n_shortcut = (int64_t)c[1];
+        out->n_fallback = (int64_t)c[2];
+        out->step = h->step;
+        if (out->n_bad > 0) status = set_err(h, LBM3_EUNSTABLE, "NaN or non-positive density in the state");
+    }
+    if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return hip_err(h, e, "observe");
+    return status;
+}
+
+lbm3_status lbm3_contact_angle(lbm3 *h, int32_t comp, int32_t wall, double exclude, double *out)
+{
+    if (!h) return LBM3_EINVAL;
+    if (!h->inited) return set_err(h, LBM3_ESTATE, "contact angle before init");
+    if (!out || (comp != 2 && comp != 3) || (wall != 0 && wall != 1) || !h->kp.walls)
+        return set_err(h, LBM3_EINVAL, "contact angle needs comp 2 or 3, wall 0 or 1, a walled grid");
+    const KParams &k = h->kp;
+    hipError_t e;
+    if (lbm3k::launch_moments(k, h->prec, h->b, h->pc, h->fc, h->stream) ||
+        lbm3k::launch_contour(k, h->prec, h->b, 1 - h->fc, comp, wall, exclude, h->stream))
+        return set_err(h, LBM3_EDEVICE, "contour launch failed");
+    double r[16];
+    if ((e = hipMemcpyAsync(r, h->b.result, sizeof(r), hipMemcpyDeviceToHost, h->stream)) != hipSuccess)
+        return hip_err(h, e, "contour download");
+    if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return hip_err(h, e, "contour");
+    // normal equations of the Kasa fit, unknowns (D, E, [F,] G)
+    int m = k.D == 2 ? 3 : 4;
+    double A[4][5];
+    int idx = 0;
+    for (int a = 0; a < m; ++a)
+        for (int bb = a; bb < m; ++bb) { A[a][bb] = A[bb][a] = r[idx++]; }
+    for (int a = 0; a < m; ++a) A[a][m] = -r[idx++];
+    double npts = A[m - 1][m - 1];
+    if (npts < m + 1) return set_err(h, LBM3_EINVAL, "too few contour points for a circle fit");
+    for (int c = 0; c < m; ++c) {  // Gaussian elimination with partial pivoting
+        int piv = c;
+        for (int rr = c + 1; rr < m; ++rr)
+            if (std::fabs(A[rr][c]) > std::fabs(A[piv][c])) piv = rr;
+        for (int cc = 0; cc <= m; ++cc) std::swap(A[c][cc], A[piv][cc]);
+        for (int rr = 0; rr < m; ++rr) {
+            if (rr == c) continue;
+            double f = A[rr][c] / A[c][c];
+            for (int cc = c; cc <= m; ++cc) A[rr][cc] -= f * A[c][cc];
+        }
+    }
+    double sol[4];
+    for (int a = 0; a < m; ++a) sol[a] = A[a][m] / A[a][a];
+    double cen[3] = {0, 0, 0}, rr2 = 0;
+    for (int a = 0; a < m - 1; ++a) { cen[a] = -0.5 * sol[a]; rr2 += cen[a] * cen[a]; }
+    double R = std::sqrt(rr2 - sol[m - 1]);
+    double wplane = wall == 0 ? 0.5 : k.nw - 1.5;
+    double hc = cen[k.D - 1];
+    double hgt = wall == 0 ? hc - wplane : wplane - hc;
+    double cth = -hgt / R;
+    cth = cth > 1 ? 1 : (cth < -1 ? -1 : cth);
+    out[0] = std::acos(cth) * 180.0 / PI;
+    out[1] = cen[0];
+    out[2] = cen[1];
+    out[3] = cen[2];
+    out[4] = R;
+    out[5] = npts;
+    return LBM3_OK;
+}
+
+lbm3_status lbm3_destroy(lbm3 *h)
+{
+    if (!h) return LBM3_EINVAL;
+    delete h;
+    return LBM3_OK;
+}
+
+const char *lbm3_last_error(const lbm3 *h)
+{
+    return h ? h->err.c_str() : g_create_err.c_str();
+}
+
+}  // extern "C"

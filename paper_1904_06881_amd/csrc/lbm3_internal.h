@@ -1,0 +1,57 @@
+// Internal declarations of the lbm3 HIP library (not part of the C ABI).
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+
+namespace lbm3k {
+
+// Everything the kernels need, passed by value as a kernel argument.
+struct KParams {
+    int D, Q;            // 2/9 or 3/27
+    int nx, ny, nz;      // grid
+    int nw;              // extent of the wall (last) axis
+    int walls;           // 1: ghost layers at 0 and nw-1 of the last axis
+    long long N;         // nodes
+    long long PS;        // plane stride of the last axis (nx or nx*ny)
+    double rho_l, rho_g, drho, chi;
+    double a, b, T, C, psi0;
+    double lam1, lam2, lam3;
+    double krr, kpp, kx;         // gradient mixing coefficients
+    double beta, inv_tau_g, Gamma;
+    int wetting;                 // 0 force, 1 geometric interpolation, 2 extrapolation
+    double cot[2][3];            // per wall: cot(theta21), cot(theta31), cot(theta23)
+    double kw[2][2];             // per wall: kappa_rho^w, kappa_phi^w
+    double alpha_eps, alpha_tol;
+    int alpha_maxit;
+    unsigned flags;              // 1 no-collide, 2 alpha = 2
+};
+
+enum Prec { P64 = 0, P32 = 1, P16 = 2 };
+
+// Device buffers of one simulation, carved out of the caller's workspace.
+struct Buffers {
+    void *f[2], *g[2];           // populations [Q][N], storage type by precision
+    void *rho[2], *phi[2];       // fields [N], compute type
+    double *scratch;             // N doubles (upload / export staging)
+    unsigned long long *counters;// 4: newton, shortcut, fallback, spare
+    double *partials;            // reduction partials
+    double *result;              // 32 doubles of reduced observables
+    int n_partials;              // capacity in blocks
+};
+
+// Launchers (lbm3_kernels.hip).  All asynchronous on `stream`.
+int launch_moments(const KParams &kp, int prec, const Buffers &b, int pc, int fc, void *stream);
+int launch_ghost(const KParams &kp, int prec, const Buffers &b, int fdst, void *stream);
+int launch_fused(const KParams &kp, int prec, const Buffers &b, int pc, int fc, void *stream);
+int launch_init(const KParams &kp, int prec, const Buffers &b, void *stream);
+int launch_init_field(const KParams &kp, int prec, const Buffers &b, int which, void *stream);
+int launch_observe(const KParams &kp, int prec, const Buffers &b, int pc, int fc, void *stream);
+int launch_export_pop(const KParams &kp, int prec, const Buffers &b, int pc, int fc, int which,
+                      int i, void *stream);
+int launch_export_field(const KParams &kp, int prec, const Buffers &b, int fsrc, int which,
+                        void *stream);
+int launch_contour(const KParams &kp, int prec, const Buffers &b, int fsrc, int comp, int wall,
+                   double exclude, void *stream);
+int observe_blocks(const KParams &kp);
+
+}  // namespace lbm3k

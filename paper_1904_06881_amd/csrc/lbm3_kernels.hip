@@ -1,0 +1,1109 @@
+// HIP kernels (gfx950) of the ternary high-density-ratio free-energy LBM
+// with wetting walls (Bala et al., arXiv:1904.06881).
+//
+// Data layout in HBM: populations SoA [Q][N] (x fastest), two buffers per
+// set (push streaming writes the other one); fields rho, phi [N] in the
+// compute type, two buffers (the FP16 storage decodes with the previous
+// step's fields).  A step is three launches:
+//   k_moments  rho, phi of every fluid node from its populations;
+//   k_ghost    wall ghost layers of rho, phi;
+//   k_fused    per block an in-plane tile (x in 2D, x-y in 3D) marching along
+//              the wall axis: a 5-plane LDS ring of rho, phi with halo 2, a
+//              3-plane LDS ring of -P and mu_phi with halo 1, then force,
+//              entropic collision of f, LBGK of g and push streaming with
+//              halfway bounce-back for one plane at a time.
+#include <hip/hip_runtime.h>
+
+#include "lbm3_internal.h"
+
+namespace lbm3k {
+
+// ------------------------------------------------------------ lattice ----
+// velocity i = sum_a (c_a + 1) 3^(D-1-a): x most significant
+__host__ __device__ constexpr int cdir(int D, int i, int a)
+{
+    return D == 2 ? (a == 0 ? i / 3 - 1 : (a == 1 ? i % 3 - 1 : 0))
+                  : (a == 0 ? i / 9 - 1 : (a == 1 ? (i / 3) % 3 - 1 : i % 3 - 1));
+}
+__host__ __device__ constexpr double w1(int c) { return c == 0 ? 2.0 / 3.0 : 1.0 / 6.0; }
+__host__ __device__ constexpr double wgt(int D, int i)
+{
+    return D == 2 ? w1(cdir(2, i, 0)) * w1(cdir(2, i, 1))
+                  : w1(cdir(3, i, 0)) * w1(cdir(3, i, 1)) * w1(cdir(3, i, 2));
+}
+// index of -P_ab in the symmetric storage: 2D xx xy yy; 3D xx xy xz yy yz zz
+__host__ __device__ constexpr int sym(int D, int a, int b)
+{
+    return D == 2 ? a + b
+                  : (a <= b ? (a == 0 ? b : (a == 1 ? 2 + b : 5)) : (b == 0 ? a : (b == 1 ? 2 + a : 5)));
+}
+
+template <int PREC> struct Ty;
+template <> struct Ty<P64> { using S = double; using R = double; };
+template <> struct Ty<P32> { using S = float; using R = float; };
+template <> struct Ty<P16> { using S = _Float16; using R = float; };
+
+__device__ __forceinline__ int wrapi(int v, int n)
+{
+    int r = v % n;
+    return r < 0 ? r + n : r;
+}
+
+// Storage codecs.  FP16: f_i stored as f_i / (w_i rho_node) - 1 and the rest
+// g as g_0 - phi_node, with rho_node, phi_node the fields the writer holds
+// for the node the value is stored at; other g raw.
+template <int PREC, int D>
+__device__ __forceinline__ typename Ty<PREC>::R dec_f(typename Ty<PREC>::S s, int i,
+                                                      typename Ty<PREC>::R rn)
+{
+    using R = typename Ty<PREC>::R;
+    if constexpr (PREC == P16) return (R)wgt(D, i) * rn * ((R)1 + (R)s);
+    else return (R)s;
+}
+template <int PREC, int D>
+__device__ __forceinline__ typename Ty<PREC>::S enc_f(typename Ty<PREC>::R v, int i,
+                                                      typename Ty<PREC>::R rn)
+{
+    using S = typename Ty<PREC>::S;
+    using R = typename Ty<PREC>::R;
+    if constexpr (PREC == P16) return (S)(v / ((R)wgt(D, i) * rn) - (R)1);
+    else return (S)v;
+}
+template <int PREC, int D>
+__device__ __forceinline__ typename Ty<PREC>::R dec_g(typename Ty<PREC>::S s, int i,
+                                                      typename Ty<PREC>::R pn)
+{
+    using R = typename Ty<PREC>::R;
+    constexpr int rest = (D == 2 ? 9 : 27) / 2;
+    if constexpr (PREC == P16) return i == rest ? (R)s + pn : (R)s;
+    else return (R)s;
+}
+template <int PREC, int D>
+__device__ __forceinline__ typename Ty<PREC>::S enc_g(typename Ty<PREC>::R v, int i,
+                                                      typename Ty<PREC>::R pn)
+{
+    using S = typename Ty<PREC>::S;
+    constexpr int rest = (D == 2 ? 9 : 27) / 2;
+    if constexpr (PREC == P16) return i == rest ? (S)(v - pn) : (S)v;
+    else return (S)v;
+}
+
+// ------------------------------------------------------ thermodynamics ---
+template <typename R> struct Thermo {
+    R rho_l, drho, inv_drho, chi, inv_chi, a, b, T, C, psi0, hl1, hl2, hl3, lam2, lam3, krr, kpp, kx;
+    __device__ void load(const KParams &k)
+    {
+        rho_l = (R)k.rho_l; drho = (R)k.drho; inv_drho = (R)(1.0 / k.drho);
+        chi = (R)k.chi; inv_chi = (R)(1.0 / k.chi);
+        a = (R)k.a; b = (R)k.b; T = (R)k.T; C = (R)k.C; psi0 = (R)k.psi0;
+        hl1 = (R)(0.5 * k.lam1); hl2 = (R)(0.5 * k.lam2); hl3 = (R)(0.5 * k.lam3);
+        lam2 = (R)k.lam2; lam3 = (R)k.lam3;
+        krr = (R)k.krr; kpp = (R)k.kpp; kx = (R)k.kx;
+    }
+};
+
+template <typename R> __device__ __forceinline__ R gfun(R x) { return x * (x - (R)0.5) * (x - (R)1); }
+
+// Bulk chemical potentials and free energy (Eqs. 2, 4-7, 11-12, 15): C1 from
+// rho, C2/C3 from rho and phi; dPsi and Psi of the Carnahan-Starling EOS; the
+// rho derivative of the lambda2/lambda3 wells is +(lambda2 g(C2) +
+// lambda3 g(C3))/Delta_rho (dC2/drho = dC3/drho = 1/(2 Delta_rho)).
+template <typename R>
+__device__ __forceinline__ void bulk(const Thermo<R> &t, R rho, R phi, R &mrb, R &mpb, R &fb)
+{
+    R C1 = (t.rho_l - rho) * t.inv_drho;
+    R ph = phi * t.inv_chi;
+    R C2 = (R)0.5 * ((R)1 + ph - C1);
+    R C3 = (R)0.5 * ((R)1 - ph - C1);
+    R br = t.b * rho;
+    R d = br - (R)4;
+    R id = (R)1 / d;
+    R lr = log(rho);
+    R dpsi = t.C - (R)2 * t.a * rho + t.T * ((R)1 + lr) + (R)16 * t.T * (br - (R)12) * id * id * id;
+    R psi = rho * (t.C - t.a * rho - (R)8 * t.T * (br - (R)6) * id * id + t.T * lr);
+    R g2 = gfun(C2), g3 = gfun(C3);
+    mrb = t.hl1 * dpsi + (t.lam2 * g2 + t.lam3 * g3) * t.inv_drho;
+    mpb = (t.lam2 * g2 - t.lam3 * g3) * t.inv_chi;
+    R a2 = C2 * ((R)1 - C2), a3 = C3 * ((R)1 - C3);
+    fb = t.hl1 * (psi - t.psi0) + t.hl2 * a2 * a2 + t.hl3 * a3 * a3;
+}
+
+// mu_rho, mu_phi (Eqs. 11-18 with one cross coefficient k_x) and -P
+// (Eqs. 19-20) from the fields and their stencils.  NP = D(D+1)/2.
+template <int D, typename R>
+__device__ __forceinline__ void thermo(const Thermo<R> &t, R rho, R phi, const R *G, const R *H,
+                                       R Lr, R Lp, R &mur, R &mup, R *mP)
+{
+    R mrb, mpb, fb;
+    bulk(t, rho, phi, mrb, mpb, fb);
+    mur = mrb - t.krr * Lr - t.kx * Lp;
+    mup = mpb - t.kpp * Lp - t.kx * Lr;
+    R p0 = rho * mrb + phi * mpb - fb;
+    R GG = 0, HH = 0, GH = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) { GG += G[a] * G[a]; HH += H[a] * H[a]; GH += G[a] * H[a]; }
+    R iso = p0 - t.krr * (rho * Lr + (R)0.5 * GG) - t.kpp * (phi * Lp + (R)0.5 * HH) -
+            t.kx * (rho * Lp + phi * Lr + GH);
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = a; b < D; ++b) {
+            R v = t.krr * G[a] * G[b] + t.kpp * H[a] * H[b] + t.kx * (G[a] * H[b] + H[a] * G[b]);
+            if (a == b) v += iso;
+            mP[sym(D, a, b)] = -v;
+        }
+}
+
+// Link pressure of the ideal part of the force: equals rho/3 for equal
+// densities; its lattice divergence keeps an exponential density profile an
+// exact steady state of the product-form ELBM.
+template <typename R> __device__ __forceinline__ R link_p(R rx, R ry)
+{
+    return (R)2 * rx * ry / (rx + ry + (R)4 * sqrt(rx * ry));
+}
+
+// ------------------------------------------------------------ equilibria -
+// f_i^eq = rho w_i prod_a A(u_a) B(u_a)^{c_ia}, Eqs. 25-27.
+template <int D, typename R>
+__device__ __forceinline__ void feq(R rho, const R *u, R *fe)
+{
+    constexpr int Q = D == 2 ? 9 : 27;
+    R fac[3][3];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        R s = sqrt((R)1 + (R)3 * u[a] * u[a]);
+        R A = (R)2 - s;
+        R B = ((R)2 * u[a] + s) / ((R)1 - u[a]);
+        fac[a][0] = (R)(1.0 / 6.0) * A / B;
+        fac[a][1] = (R)(2.0 / 3.0) * A;
+        fac[a][2] = (R)(1.0 / 6.0) * A * B;
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        R v = rho * fac[0][cdir(D, i, 0) + 1] * fac[1][cdir(D, i, 1) + 1];
+        if constexpr (D == 3) v *= fac[2][cdir(D, i, 2) + 1];
+        fe[i] = v;
+    }
+}
+
+// Entropic alpha: non-trivial root of H(f' + alpha Delta) = H(f'), Eqs. 30-32,
+// as G(alpha) = sum f'[(1 + alpha x) log1p(alpha x) - alpha x (1 + log1p(x))]
+// with x = Delta/f': the terms linear in ln(f^eq/w) and alpha sum Delta vanish
+// because Delta carries no mass or momentum, and leaving them out keeps the
+// root free of their rounding.  kind: 0 small deviation (max|x| < eps, root
+// from the expansion of G about alpha = 2: 2 + (S3 - 2 S4)/(3 S2 - 4 S3),
+// S_k = sum f' x^k), 1 Newton root, 2 fallback (non-positive f' or no
+// convergence).  Iterates are kept in (1, alpha_max), alpha_max = min_{x<0}
+// -1/x the positivity limit.  On return dx holds x (is_x = true) or, after a
+// non-positive f', still Delta.
+template <int Q, typename R>
+__device__ __forceinline__ R entropic_alpha(const R *fp, R *dx, R eps, R tol, int maxit, int &kind,
+                                            bool &is_x)
+{
+    bool pos = true;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) pos = pos && (fp[i] > (R)0);
+    if (!pos) { kind = 2; is_x = false; return (R)2; }
+    is_x = true;
+    R xmax = 0, amax = (R)INFINITY;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        dx[i] = dx[i] / fp[i];
+        xmax = fmax(xmax, fabs(dx[i]));
+        if (dx[i] < (R)0) amax = fmin(amax, (R)-1 / dx[i]);
+    }
+    if (xmax < eps) {
+        kind = 0;
+        R S2 = 0, S3 = 0, S4 = 0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            R x2 = dx[i] * dx[i];
+            S2 += fp[i] * x2;
+            S3 += fp[i] * x2 * dx[i];
+            S4 += fp[i] * x2 * x2;
+        }
+        R den = (R)3 * S2 - (R)4 * S3;
+        return den > (R)0 ? (R)2 + (S3 - (R)2 * S4) / den : (R)2;
+    }
+    R l1[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) l1[i] = log1p(dx[i]);
+    R al = ((R)2 < amax) ? (R)2 : (R)0.5 * ((R)1 + amax);
+    for (int it = 0; it < maxit; ++it) {
+        R G = 0, dG = 0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            R ax = al * dx[i];
+            R la = log1p(ax);
+            G += fp[i] * (((R)1 + ax) * la - ax * ((R)1 + l1[i]));
+            dG += fp[i] * dx[i] * (la - l1[i]);
+        }
+        if (!(dG > (R)0)) break;
+        R an = al - G / dG;
+        if (an >= amax) an = (R)0.5 * (al + amax);
+        if (an <= (R)1) an = (R)0.5 * (al + (R)1);
+        if (fabs(an - al) < tol) { kind = 1; return an; }
+        al = an;
+    }
+    kind = 2;
+    return ((R)2 < amax) ? (R)2 : amax;
+}
+
+// -------------------------------------------------------------- moments --
+template <int D, int PREC>
+__global__ void __launch_bounds__(256)
+k_moments(KParams kp, const typename Ty<PREC>::S *__restrict__ f, const typename Ty<PREC>::S *__restrict__ g,
+          const typename Ty<PREC>::R *__restrict__ rprev, const typename Ty<PREC>::R *__restrict__ pprev,
+          typename Ty<PREC>::R *__restrict__ rho, typename Ty<PREC>::R *__restrict__ phi)
+{
+    using R = typename Ty<PREC>::R;
+    constexpr int Q = D == 2 ? 9 : 27;
+    long long first = kp.walls ? kp.PS : 0;
+    long long count = kp.walls ? kp.N - 2 * kp.PS : kp.N;
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count) return;
+    long long n = first + t;
+    R rp = (R)0, pp = (R)0;
+    if constexpr (PREC == P16) { rp = rprev[n]; pp = pprev[n]; }
+    R r = 0, ph = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        r += dec_f<PREC, D>(f[(long long)i * kp.N + n], i, rp);
+        ph += dec_g<PREC, D>(g[(long long)i * kp.N + n], i, pp);
+    }
+    rho[n] = r;
+    phi[n] = ph;
+}
+
+// ----------------------------------------------------------- ghost layers
+// Interface detection (paper's rules, cascade 1-3 then 4-5 override):
+// 0 = 1-2 (theta21), 1 = 1-3 (theta31), 2 = 2-3 (theta23).
+template <typename R>
+__device__ __forceinline__ int classify(R ngr, R ngp, R dot, R r, R ph, R rho_l, R drho, R chi)
+{
+    int k;
+    if (ngr * chi < (R)0.01 * drho * ngp) k = 2;
+    else if (dot < (R)0) k = 1;
+    else k = 0;
+    if (r > (R)0.5 * rho_l && ph < (R)-0.95 * chi) k = 1;
+    if (r > (R)0.5 * rho_l && ph > (R)0.95 * chi) k = 0;
+    return k;
+}
+
+template <typename R>
+__device__ __forceinline__ R interp2(const R *q, long long base, int nx, int i, R l)
+{
+    R l0 = floor(l), l1 = l0 + (R)1;
+    R q0 = q[base + wrapi(i + (int)l0, nx)];
+    if (l == l0) return q0;  // exact lattice copy at integer shifts
+    R q1 = q[base + wrapi(i + (int)l1, nx)];
+    return (q1 - q0) * l + (l1 * q0 - l0 * q1);
+}
+
+// plane through the three corners of the unit cell nearest to (lx, ly),
+// Eqs. 48-49
+template <typename R>
+__device__ __forceinline__ R interp3(const R *q, long long base, int nx, int ny, int i, int j, R lx, R ly)
+{
+    R x0 = floor(lx), y0 = floor(ly);
+    R fx = lx - x0, fy = ly - y0;
+    const int cx[4] = {0, 1, 0, 1}, cy[4] = {0, 0, 1, 1};
+    int drop = 0;
+    R dmax = (R)-1;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        R d = (fx - cx[k]) * (fx - cx[k]) + (fy - cy[k]) * (fy - cy[k]);
+        if (d > dmax) { dmax = d; drop = k; }
+    }
+    R X[3], Y[3], Cv[3];
+    int m = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (k == drop) continue;
+        X[m] = x0 + cx[k];
+        Y[m] = y0 + cy[k];
+        Cv[m] = q[base + wrapi(i + (int)X[m], nx) + (long long)nx * wrapi(j + (int)Y[m], ny)];
+        ++m;
+    }
+    R x1 = X[0], x2 = X[1], x3 = X[2], y1 = Y[0], y2 = Y[1], y3 = Y[2];
+    R c1 = Cv[0], c2 = Cv[1], c3 = Cv[2];
+    R A = y2 * c1 - y3 * c1 - y1 * c2 + y3 * c2 + y1 * c3 - y2 * c3;
+    R B = -x2 * c1 + x3 * c1 + x1 * c2 - x3 * c2 - x1 * c3 + x2 * c3;
+    R Cc = -x3 * y2 * c1 + x2 * y3 * c1 + x3 * y1 * c2 - x1 * y3 * c2 - x2 * y1 * c3 + x1 * y2 * c3;
+    R Dd = -x2 * y1 + x3 * y1 + x1 * y2 - x3 * y2 - x1 * y3 + x2 * y3;
+    return (A * lx + B * ly + Cc) / Dd;
+}
+
+template <int D, typename R>
+__global__ void __launch_bounds__(256)
+k_ghost(KParams kp, R *__restrict__ rho, R *__restrict__ phi)
+{
+    int nx = kp.nx, ny = kp.ny;
+    int np = (D == 2) ? nx : nx * ny;  // ghost nodes per wall
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 2 * np) return;
+    int wall = t / np;
+    int k = t % np;
+    int i = k % nx, j = (D == 2) ? 0 : k / nx;
+    int kg = wall == 0 ? 0 : kp.nw - 1, kf = wall == 0 ? 1 : kp.nw - 2;
+    long long bf = (long long)kf * kp.PS, bg = (long long)kg * kp.PS;
+    long long nf = bf + i + (long long)nx * j, ng = bg + i + (long long)nx * j;
+    R r0 = rho[nf], p0 = phi[nf];
+    if (kp.wetting == 0) { rho[ng] = r0; phi[ng] = p0; return; }
+    R drho = (R)kp.drho, chi = (R)kp.chi;
+    R gr[2] = {0, 0}, gp[2] = {0, 0};
+    gr[0] = (R)0.5 * (rho[bf + wrapi(i + 1, nx) + (long long)nx * j] - rho[bf + wrapi(i - 1, nx) + (long long)nx * j]);
+    gp[0] = (R)0.5 * (phi[bf + wrapi(i + 1, nx) + (long long)nx * j] - phi[bf + wrapi(i - 1, nx) + (long long)nx * j]);
+    if constexpr (D == 3) {
+        gr[1] = (R)0.5 * (rho[bf + i + (long long)nx * wrapi(j + 1, ny)] - rho[bf + i + (long long)nx * wrapi(j - 1, ny)]);
+        gp[1] = (R)0.5 * (phi[bf + i + (long long)nx * wrapi(j + 1, ny)] - phi[bf + i + (long long)nx * wrapi(j - 1, ny)]);
+    }
+    R ngr = sqrt(gr[0] * gr[0] + gr[1] * gr[1]);
+    R ngp = sqrt(gp[0] * gp[0] + gp[1] * gp[1]);
+    R out_r = r0, out_p = p0;
+    if (!(ngr < (R)1e-12 * drho && ngp < (R)1e-12 * drho)) {
+        R dot = gr[0] * gp[0] + gr[1] * gp[1];
+        int cls = classify(ngr, ngp, dot, r0, p0, (R)kp.rho_l, drho, chi);
+        R ct = (R)kp.cot[wall][cls];
+        const R *gc = cls == 2 ? gp : gr;
+        R ngc = cls == 2 ? ngp : ngr;
+        if (kp.wetting == 2) {
+            // geometric extrapolation (Eqs. 45-46), per field along m
+            if (ngc != (R)0) {
+                R m0 = gc[0] / ngc, m1 = gc[1] / ngc;
+                out_r = r0 + ct * (gr[0] * m0 + gr[1] * m1);
+                out_p = p0 + ct * (gp[0] * m0 + gp[1] * m1);
+            }
+        } else if constexpr (D == 2) {
+            // shift by cot(theta) toward the measuring phase (+grad c)
+            R sg = gc[0] > (R)0 ? (R)1 : (gc[0] < (R)0 ? (R)-1 : (R)0);
+            R l = sg * ct;
+            out_r = interp2(rho, bf, nx, i, l);
+            out_p = interp2(phi, bf, nx, i, l);
+        } else {
+            if (ngc != (R)0) {
+                R lx = ct * gc[0] / ngc, ly = ct * gc[1] / ngc;
+                out_r = interp3(rho, bf, nx, ny, i, j, lx, ly);
+                out_p = interp3(phi, bf, nx, ny, i, j, lx, ly);
+            }
+        }
+    }
+    rho[ng] = out_r;
+    phi[ng] = out_p;
+}
+
+// ---------------------------------------------------------------- fused --
+template <int D, int PREC, int TX, int TY>
+__global__ void __launch_bounds__(TX * TY)
+k_fused(KParams kp, const typename Ty<PREC>::S *__restrict__ fin, const typename Ty<PREC>::S *__restrict__ gin,
+        typename Ty<PREC>::S *__restrict__ fout, typename Ty<PREC>::S *__restrict__ gout,
+        const typename Ty<PREC>::R *__restrict__ rho, const typename Ty<PREC>::R *__restrict__ phi,
+        const typename Ty<PREC>::R *__restrict__ rprev, const typename Ty<PREC>::R *__restrict__ pprev,
+        unsigned long long *__restrict__ cnt, int chunk)
+{
+    using R = typename Ty<PREC>::R;
+    constexpr int Q = D == 2 ? 9 : 27;
+    constexpr int NTH = TX * TY;
+    constexpr int FW = TX + 4, FH = D == 3 ? TY + 4 : 1, FS = FW * FH;
+    constexpr int TW = TX + 2, TH = D == 3 ? TY + 2 : 1, TS = TW * TH;
+    constexpr int NP = D * (D + 1) / 2;
+    constexpr int WA = D - 1;  // wall (march) axis component
+    __shared__ R s_r[5][FS];
+    __shared__ R s_p[5][FS];
+    __shared__ R s_t[3][NP + 1][TS];
+    __shared__ int s_cnt[3];
+
+    const int tid = threadIdx.x;
+    const int nx = kp.nx, ny = kp.ny, nw = kp.nw;
+    const int ntx = (nx + TX - 1) / TX;
+    const int x0 = (blockIdx.x % ntx) * TX;
+    const int y0 = (D == 3) ? (blockIdx.x / ntx) * TY : 0;
+    const int pf0 = kp.walls ? 1 : 0, pf1 = kp.walls ? nw - 1 : nw;
+    const int pb = pf0 + blockIdx.y * chunk;
+    const int pe = min(pb + chunk, pf1);
+    if (pb >= pe) return;
+    if (tid < 3) s_cnt[tid] = 0;
+
+    Thermo<R> th;
+    th.load(kp);
+    const R beta = (R)kp.beta, itg = (R)kp.inv_tau_g, Gam = (R)kp.Gamma;
+    const R aeps = (R)kp.alpha_eps, atol = (R)kp.alpha_tol;
+    const bool collide = !(kp.flags & 1u), alpha2 = (kp.flags & 2u) != 0;
+
+    auto fvalid = [&](int q) { return kp.walls ? (q >= 0 && q <= nw - 1) : true; };
+    auto tvalid = [&](int q) { return kp.walls ? (q >= 1 && q <= nw - 2) : true; };
+    auto plane = [&](int q) { return kp.walls ? q : wrapi(q, nw); };
+
+    auto load_fields = [&](int q) {
+        if (!fvalid(q)) return;
+        int slot = (q + 10) % 5;
+        long long base = (long long)plane(q) * kp.PS;
+        for (int k = tid; k < FS; k += NTH) {
+            int lx = k % FW, ly = k / FW;
+            int gx = wrapi(x0 + lx - 2, nx);
+            long long n = base + gx;
+            if constexpr (D == 3) n += (long long)nx * wrapi(y0 + ly - 2, ny);
+            s_r[slot][k] = rho[n];
+            s_p[slot][k] = phi[n];
+        }
+    };
+
+    auto compute_T = [&](int q) {
+        if (!tvalid(q)) return;
+        int st = (q + 10) % 3;
+        int sm = (q + 9) % 5, s0 = (q + 10) % 5, sp = (q + 11) % 5;
+        for (int k = tid; k < TS; k += NTH) {
+            int hx = k % TW, hy = k / TW;
+            int fc = (D == 3 ? (hy + 1) * FW : 0) + hx + 1;
+            R G[3] = {0, 0, 0}, H[3] = {0, 0, 0}, Lr = 0, Lp = 0;
+            R r0 = s_r[s0][fc], p0 = s_p[s0][fc];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const int cw = cdir(D, i, WA);
+                const int off = cdir(D, i, 0) + (D == 3 ? cdir(D, i, 1) * FW : 0);
+                const int sl = cw < 0 ? sm : (cw > 0 ? sp : s0);
+                R rn = s_r[sl][fc + off], pn = s_p[sl][fc + off];
+                const R w3 = (R)(3.0 * wgt(D, i));
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    if (cdir(D, i, a) != 0) {
+                        G[a] += w3 * (R)cdir(D, i, a) * rn;
+                        H[a] += w3 * (R)cdir(D, i, a) * pn;
+                    }
+                }
+                if (i != Q / 2) {
+                    Lr += (R)(6.0 * wgt(D, i)) * (rn - r0);
+                    Lp += (R)(6.0 * wgt(D, i)) * (pn - p0);
+                }
+            }
+            R mur, mup, mP[NP];
+            thermo<D, R>(th, r0, p0, G, H, Lr, Lp, mur, mup, mP);
+#pragma unroll
+            for (int c = 0; c < NP; ++c) s_t[st][c][k] = mP[c];
+            s_t[st][NP][k] = mup;
+        }
+    };
+
+    // prologue: fields pb-2 .. pb+1, -P planes pb-1 .. pb
+    for (int q = pb - 2; q <= pb + 1; ++q) load_fields(q);
+    __syncthreads();
+    compute_T(pb - 1);
+    compute_T(pb);
+
+    const int tx = tid % TX, ty = tid / TX;
+    const int x = x0 + tx, y = y0 + ty;
+    const bool active = x < nx && (D == 2 || y < ny);
+    const int fcen = (D == 3 ? (ty + 2) * FW : 0) + tx + 2;
+    const int tcen = (D == 3 ? (ty + 1) * TW : 0) + tx + 1;
+    int my_cnt[3] = {0, 0, 0};
+
+    for (int p = pb; p < pe; ++p) {
+        load_fields(p + 2);
+        __syncthreads();
+        compute_T(p + 1);
+        __syncthreads();
+        if (active) {
+            const int sm = (p + 9) % 5, s0 = (p + 10) % 5, sp = (p + 11) % 5;
+            const int tm = (p + 9) % 3, t0 = (p + 10) % 3, tp = (p + 11) % 3;
+            const R r0 = s_r[s0][fcen], p0 = s_p[s0][fcen];
+            const bool first = kp.walls && (p == 1 || p == nw - 2);
+            R F[3] = {0, 0, 0};
+            if (first) {
+                // wall rule: normal derivatives dropped, in-layer differences
+#pragma unroll
+                for (int b = 0; b < D - 1; ++b) {
+                    const int ot = b == 0 ? 1 : TW, of = b == 0 ? 1 : FW;
+#pragma unroll
+                    for (int a = 0; a < D; ++a)
+                        F[a] += (R)0.5 * (s_t[t0][sym(D, a, b)][tcen + ot] - s_t[t0][sym(D, a, b)][tcen - ot]);
+                    F[b] += link_p(r0, s_r[s0][fcen + of]) - link_p(r0, s_r[s0][fcen - of]);
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < Q; ++i) {
+                    if (i == Q / 2) continue;
+                    const int cw = cdir(D, i, WA);
+                    const int offt = cdir(D, i, 0) + (D == 3 ? cdir(D, i, 1) * TW : 0);
+                    const int offf = cdir(D, i, 0) + (D == 3 ? cdir(D, i, 1) * FW : 0);
+                    const int slt = cw < 0 ? tm : (cw > 0 ? tp : t0);
+                    const int slf = cw < 0 ? sm : (cw > 0 ? sp : s0);
+                    const R w3 = (R)(3.0 * wgt(D, i)), w6 = (R)(6.0 * wgt(D, i));
+                    const R pl = link_p(r0, s_r[slf][fcen + offf]);
+#pragma unroll
+                    for (int a = 0; a < D; ++a) {
+                        R acc = 0;
+#pragma unroll
+                        for (int b = 0; b < D; ++b)
+                            if (cdir(D, i, b) != 0) acc += (R)cdir(D, i, b) * s_t[slt][sym(D, a, b)][tcen + offt];
+                        F[a] += w3 * acc;
+                        if (cdir(D, i, a) != 0) F[a] += w6 * (R)cdir(D, i, a) * pl;
+                    }
+                }
+            }
+            if (kp.walls && kp.wetting == 0) {
+                R rrel = (r0 - (R)kp.rho_g) * th.inv_drho, prel = p0 * th.inv_chi;
+                if (p == 2) F[WA] -= (R)(1.0 / 6.0) * rrel * ((R)kp.kw[0][0] + prel * (R)kp.kw[0][1]);
+                if (p == nw - 3) F[WA] += (R)(1.0 / 6.0) * rrel * ((R)kp.kw[1][0] + prel * (R)kp.kw[1][1]);
+            }
+            const long long n = (long long)p * kp.PS + x + (D == 3 ? (long long)nx * y : 0);
+            R rp = (R)0, pp = (R)0;
+            if constexpr (PREC == P16) { rp = rprev[n]; pp = pprev[n]; }
+            R f[Q];
+            R j[3] = {0, 0, 0};
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                f[i] = dec_f<PREC, D>(fin[(long long)i * kp.N + n], i, rp);
+#pragma unroll
+                for (int a = 0; a < D; ++a)
+                    if (cdir(D, i, a) != 0) j[a] += (R)cdir(D, i, a) * f[i];
+            }
+            R u[3], ud[3], v[3];
+            const R ir = (R)1 / r0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                u[a] = j[a] * ir;
+                R du = F[a] * ir;
+                ud[a] = u[a] + du;
+                v[a] = u[a] + (R)0.5 * du;
+            }
+            if (collide) {
+                R fe[Q], fd[Q];
+                feq<D, R>(r0, u, fe);
+                feq<D, R>(r0, ud, fd);
+#pragma unroll
+                for (int i = 0; i < Q; ++i) {
+                    R fpi = f[i] + fd[i] - fe[i];
+                    fe[i] = fd[i] - fpi;  // Delta
+                    f[i] = fpi;           // mirror state f'
+                }
+                R al = (R)2;
+                bool is_x = false;
+                if (!alpha2) {
+                    int kind;
+                    al = entropic_alpha<Q, R>(f, fe, aeps, atol, kp.alpha_maxit, kind, is_x);
+                    my_cnt[kind == 1 ? 0 : (kind == 0 ? 1 : 2)]++;
+                }
+                const R ab = al * beta;
+                if (is_x) {
+#pragma unroll
+                    for (int i = 0; i < Q; ++i) f[i] += ab * (fe[i] * f[i]);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < Q; ++i) f[i] += ab * fe[i];
+                }
+            }
+            // stream f: push to x + c_i, halfway bounce-back at the walls
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const int cw = cdir(D, i, WA);
+                const int pt = p + cw;
+                if (kp.walls && (pt < 1 || pt > nw - 2)) {
+                    fout[(long long)(Q - 1 - i) * kp.N + n] = enc_f<PREC, D>(f[i], Q - 1 - i, r0);
+                } else {
+                    const int offf = cdir(D, i, 0) + (D == 3 ? cdir(D, i, 1) * FW : 0);
+                    const int slf = cw < 0 ? sm : (cw > 0 ? sp : s0);
+                    const long long nt = (long long)plane(pt) * kp.PS + wrapi(x + cdir(D, i, 0), nx) +
+                                         (D == 3 ? (long long)nx * wrapi(y + cdir(D, i, 1), ny) : 0);
+                    fout[(long long)i * kp.N + nt] = enc_f<PREC, D>(f[i], i, s_r[slf][fcen + offf]);
+                }
+            }
+            // g: LBGK toward g^eq(phi, v) (Eqs. 33-35)
+            R gg[Q];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) gg[i] = dec_g<PREC, D>(gin[(long long)i * kp.N + n], i, pp);
+            if (collide) {
+                const R mup = s_t[t0][NP][tcen];
+                R vv = 0;
+#pragma unroll
+                for (int a = 0; a < D; ++a) vv += v[a] * v[a];
+                R sum = 0;
+                R ge[Q];
+#pragma unroll
+                for (int i = 0; i < Q; ++i) {
+                    if (i == Q / 2) continue;
+                    R vc = 0;
+#pragma unroll
+                    for (int a = 0; a < D; ++a)
+                        if (cdir(D, i, a) != 0) vc += (R)cdir(D, i, a) * v[a];
+                    ge[i] = (R)wgt(D, i) * ((R)3 * Gam * mup + (R)3 * p0 * vc + (R)4.5 * p0 * vc * vc -
+                                            (R)1.5 * p0 * vv);
+                    sum += ge[i];
+                }
+                ge[Q / 2] = p0 - sum;
+#pragma unroll
+                for (int i = 0; i < Q; ++i) gg[i] += (ge[i] - gg[i]) * itg;
+            }
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const int cw = cdir(D, i, WA);
+                const int pt = p + cw;
+                if (kp.walls && (pt < 1 || pt > nw - 2)) {
+                    gout[(long long)(Q - 1 - i) * kp.N + n] = enc_g<PREC, D>(gg[i], Q - 1 - i, p0);
+                } else {
+                    const int offf = cdir(D, i, 0) + (D == 3 ? cdir(D, i, 1) * FW : 0);
+                    const int slf = cw < 0 ? sm : (cw > 0 ? sp : s0);
+                    const long long nt = (long long)plane(pt) * kp.PS + wrapi(x + cdir(D, i, 0), nx) +
+                                         (D == 3 ? (long long)nx * wrapi(y + cdir(D, i, 1), ny) : 0);
+                    gout[(long long)i * kp.N + nt] = enc_g<PREC, D>(gg[i], i, s_p[slf][fcen + offf]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // alpha statistics
+    if (my_cnt[0]) atomicAdd(&s_cnt[0], my_cnt[0]);
+    if (my_cnt[1]) atomicAdd(&s_cnt[1], my_cnt[1]);
+    if (my_cnt[2]) atomicAdd(&s_cnt[2], my_cnt[2]);
+    __syncthreads();
+    if (tid < 3 && s_cnt[tid]) atomicAdd(&cnt[tid], (unsigned long long)s_cnt[tid]);
+}
+
+// ---------------------------------------------------------------- init ---
+template <typename R>
+__global__ void __launch_bounds__(256)
+k_init_fields(long long N, const double *__restrict__ src, R *__restrict__ r0, R *__restrict__ r1)
+{
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N) return;
+    R v = (R)src[t];
+    r0[t] = v;
+    r1[t] = v;
+}
+
+// f = w rho0; g = g^eq(phi0, mu_phi, 0), mu_phi from the stencils of the
+// ghost-filled initial fields.
+template <int D, int PREC>
+__global__ void __launch_bounds__(256)
+k_init_pops(KParams kp, const typename Ty<PREC>::R *__restrict__ rho, const typename Ty<PREC>::R *__restrict__ phi,
+            typename Ty<PREC>::S *__restrict__ f, typename Ty<PREC>::S *__restrict__ g)
+{
+    using R = typename Ty<PREC>::R;
+    constexpr int Q = D == 2 ? 9 : 27;
+    constexpr int WA = D - 1;
+    long long first = kp.walls ? kp.PS : 0;
+    long long count = kp.walls ? kp.N - 2 * kp.PS : kp.N;
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count) return;
+    long long n = first + t;
+    int x = (int)(n % kp.nx);
+    int y = (int)((n / kp.nx) % kp.ny);
+    int z = (int)(n / ((long long)kp.nx * kp.ny));
+    int p = (D == 2) ? y : z;
+    Thermo<R> th;
+    th.load(kp);
+    R r0 = rho[n], p0 = phi[n];
+    R G[3] = {0, 0, 0}, H[3] = {0, 0, 0}, Lr = 0, Lp = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        int q = p + cdir(D, i, WA);
+        if (!kp.walls) q = wrapi(q, kp.nw);
+        long long m = (long long)q * kp.PS + wrapi(x + cdir(D, i, 0), kp.nx) +
+                      (D == 3 ? (long long)kp.nx * wrapi(y + cdir(D, i, 1), kp.ny) : 0);
+        R rn = rho[m], pn = phi[m];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            G[a] += (R)(3.0 * wgt(D, i) * cdir(D, i, a)) * rn;
+            H[a] += (R)(3.0 * wgt(D, i) * cdir(D, i, a)) * pn;
+        }
+        Lr += (R)(6.0 * wgt(D, i)) * (rn - r0);
+        Lp += (R)(6.0 * wgt(D, i)) * (pn - p0);
+    }
+    R mur, mup, mP[D * (D + 1) / 2];
+    thermo<D, R>(th, r0, p0, G, H, Lr, Lp, mur, mup, mP);
+    R sum = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        if (i == Q / 2) continue;
+        R gi = (R)wgt(D, i) * (R)3 * (R)kp.Gamma * mup;
+        sum += gi;
+        g[(long long)i * kp.N + n] = enc_g<PREC, D>(gi, i, p0);
+        f[(long long)i * kp.N + n] = enc_f<PREC, D>((R)wgt(D, i) * r0, i, r0);
+    }
+    g[(long long)(Q / 2) * kp.N + n] = enc_g<PREC, D>(p0 - sum, Q / 2, p0);
+    f[(long long)(Q / 2) * kp.N + n] = enc_f<PREC, D>((R)wgt(D, Q / 2) * r0, Q / 2, r0);
+}
+
+// ------------------------------------------------------------- observe ---
+constexpr int OBS_THREADS = 256;
+constexpr int NSUM = 16;
+
+// per-block FP64 partial sums of the observables over fluid nodes
+template <int D, int PREC>
+__global__ void __launch_bounds__(OBS_THREADS)
+k_observe(KParams kp, const typename Ty<PREC>::S *__restrict__ f, const typename Ty<PREC>::S *__restrict__ g,
+          const typename Ty<PREC>::R *__restrict__ rprev, const typename Ty<PREC>::R *__restrict__ pprev,
+          double *__restrict__ partials)
+{
+    using R = typename Ty<PREC>::R;
+    constexpr int Q = D == 2 ? 9 : 27;
+    __shared__ double s[NSUM][OBS_THREADS];
+    double acc[NSUM];
+#pragma unroll
+    for (int k = 0; k < NSUM; ++k) acc[k] = 0.0;
+    long long first = kp.walls ? kp.PS : 0;
+    long long count = kp.walls ? kp.N - 2 * kp.PS : kp.N;
+    for (long long t = (long long)blockIdx.x * OBS_THREADS + threadIdx.x; t < count;
+         t += (long long)gridDim.x * OBS_THREADS) {
+        long long n = first + t;
+        R rp = 0, pp = 0;
+        if constexpr (PREC == P16) { rp = rprev[n]; pp = pprev[n]; }
+        double r = 0, ph = 0, j[3] = {0, 0, 0};
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            double fi = (double)dec_f<PREC, D>(f[(long long)i * kp.N + n], i, rp);
+            r += fi;
+            ph += (double)dec_g<PREC, D>(g[(long long)i * kp.N + n], i, pp);
+#pragma unroll
+            for (int a = 0; a < D; ++a)
+                if (cdir(D, i, a) != 0) j[a] += cdir(D, i, a) * fi;
+        }
+        if (!(r > 0.0) || !isfinite(r) || !isfinite(ph)) { acc[12] += 1.0; continue; }
+        double C1 = (r - kp.rho_l) / (kp.rho_g - kp.rho_l);
+        double C2 = 0.5 * (1.0 + ph / kp.chi - C1);
+        double C3 = 0.5 * (1.0 - ph / kp.chi - C1);
+        acc[0] += C1; acc[1] += C2; acc[2] += C3;
+        acc[3] += r; acc[4] += ph;
+        double uu = 0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) { acc[5 + a] += j[a]; uu += (j[a] / r) * (j[a] / r); }
+        acc[8] += 0.5 * r * uu;
+        acc[9] = fmax(acc[9], sqrt(uu));
+    }
+#pragma unroll
+    for (int k = 0; k < NSUM; ++k) s[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int w = OBS_THREADS / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+#pragma unroll
+            for (int k = 0; k < NSUM; ++k) {
+                if (k == 9) s[k][threadIdx.x] = fmax(s[k][threadIdx.x], s[k][threadIdx.x + w]);
+                else s[k][threadIdx.x] += s[k][threadIdx.x + w];
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < NSUM) partials[(long long)blockIdx.x * NSUM + threadIdx.x] = s[threadIdx.x][0];
+}
+
+// fixed-order reduction of the block partials (slot 9 is a max)
+__global__ void __launch_bounds__(NSUM)
+k_reduce(const double *__restrict__ partials, int nblocks, double *__restrict__ out)
+{
+    int k = threadIdx.x;
+    double acc = 0.0, c = 0.0;
+    for (int b = 0; b < nblocks; ++b) {
+        double v = partials[(long long)b * NSUM + k];
+        if (k == 9) { acc = fmax(acc, v); continue; }
+        double t = acc + v;  // compensated
+        c += (fabs(acc) >= fabs(v)) ? (acc - t) + v : (v - t) + acc;
+        acc = t;
+    }
+    out[k] = acc + c;
+}
+
+// plain fixed-order compensated sum of every slot
+__global__ void __launch_bounds__(NSUM)
+k_reduce_sum(const double *__restrict__ partials, int nblocks, double *__restrict__ out)
+{
+    int k = threadIdx.x;
+    double acc = 0.0, c = 0.0;
+    for (int b = 0; b < nblocks; ++b) {
+        double v = partials[(long long)b * NSUM + k];
+        double t = acc + v;
+        c += (fabs(acc) >= fabs(v)) ? (acc - t) + v : (v - t) + acc;
+        acc = t;
+    }
+    out[k] = acc + c;
+}
+
+template <int D, int PREC>
+__global__ void __launch_bounds__(256)
+k_export_pop(long long N, const typename Ty<PREC>::S *__restrict__ s, int i,
+             const typename Ty<PREC>::R *__restrict__ rprev, const typename Ty<PREC>::R *__restrict__ pprev,
+             int isg, double *__restrict__ out)
+{
+    long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    using R = typename Ty<PREC>::R;
+    R rp = 0, pp = 0;
+    if constexpr (PREC == P16) { rp = rprev[n]; pp = pprev[n]; }
+    out[n] = isg ? (double)dec_g<PREC, D>(s[(long long)i * N + n], i, pp)
+                 : (double)dec_f<PREC, D>(s[(long long)i * N + n], i, rp);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256)
+k_export_field(long long N, const R *__restrict__ s, double *__restrict__ out)
+{
+    long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n < N) out[n] = (double)s[n];
+}
+
+// Kasa least squares, FP64: per iso-point (x, y[, z]) accumulate the normal
+// equations of  x^2 + y^2 (+ z^2) + D x + E y (+ F z) + G = 0.
+template <int D, typename R>
+__global__ void __launch_bounds__(OBS_THREADS)
+k_contour(KParams kp, const R *__restrict__ rho, const R *__restrict__ phi, int comp, int wall,
+          double exclude, double *__restrict__ partials)
+{
+    __shared__ double s[NSUM][OBS_THREADS];
+    double acc[NSUM];
+#pragma unroll
+    for (int k = 0; k < NSUM; ++k) acc[k] = 0.0;
+    const int nw = kp.nw;
+    const double wplane = wall == 0 ? 0.5 : nw - 1.5;
+    auto conc = [&](long long n) {
+        double r = (double)rho[n], ph = (double)phi[n];
+        double C1 = (r - kp.rho_l) / (kp.rho_g - kp.rho_l);
+        return comp == 2 ? 0.5 * (1.0 + ph / kp.chi - C1) : 0.5 * (1.0 - ph / kp.chi - C1);
+    };
+    auto add = [&](double px, double py, double pz) {
+        double q[4] = {px, py, D == 3 ? pz : 1.0, 1.0};
+        const int m = D == 3 ? 4 : 3;
+        double rr = px * px + py * py + (D == 3 ? pz * pz : 0.0);
+        int k = 0;
+        for (int a = 0; a < m; ++a)
+            for (int b = a; b < m; ++b) acc[k++] += q[a] * q[b];
+        for (int a = 0; a < m; ++a) acc[k++] += q[a] * rr;
+    };
+    for (long long n = (long long)blockIdx.x * OBS_THREADS + threadIdx.x; n < kp.N;
+         n += (long long)gridDim.x * OBS_THREADS) {
+        int x = (int)(n % kp.nx), y = (int)((n / kp.nx) % kp.ny), z = (int)(n / ((long long)kp.nx * kp.ny));
+        int p = D == 2 ? y : z;
+        if (kp.walls && (p < 1 || p > nw - 2)) continue;
+        double c0 = conc(n) - 0.5;
+        double pos[3] = {(double)x, (double)y, (double)z};
+        for (int a = 0; a < D; ++a) {
+            int co = a == 0 ? x : (a == 1 ? y : z);
+            int na = a == 0 ? kp.nx : (a == 1 ? kp.ny : kp.nz);
+            if (co + 1 >= na) continue;
+            if (a == D - 1 && kp.walls && co + 1 > nw - 2) continue;
+            long long stride = a == 0 ? 1 : (a == 1 ? kp.nx : (long long)kp.nx * kp.ny);
+            double c1 = conc(n + stride) - 0.5;
+            double t;
+            if (c0 == 0.0 && a == 0) t = 0.0;
+            else if (c0 * c1 < 0.0) t = c0 / (c0 - c1);
+            else continue;
+            double q[3] = {pos[0], pos[1], pos[2]};
+            q[a] += t;
+            double hgt = D == 2 ? q[1] : q[2];
+            if (fabs(hgt - wplane) <= exclude) continue;
+            add(q[0], q[1], q[2]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NSUM; ++k) s[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int w = OBS_THREADS / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+#pragma unroll
+            for (int k = 0; k < NSUM; ++k) s[k][threadIdx.x] += s[k][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < NSUM) partials[(long long)blockIdx.x * NSUM + threadIdx.x] = s[threadIdx.x][0];
+}
+
+// ----------------------------------------------------------- launchers --
+#define LBM3_CHECK_LAUNCH() (hipGetLastError() == hipSuccess ? 0 : -1)
+
+template <int PREC> using SP = typename Ty<PREC>::S *;
+template <int PREC> using RP = typename Ty<PREC>::R *;
+
+static inline unsigned nblk(long long n, int t) { return (unsigned)((n + t - 1) / t); }
+
+template <int D, int PREC>
+static int moments_t(const KParams &kp, const Buffers &b, int pc, int fc, hipStream_t st)
+{
+    long long count = kp.walls ? kp.N - 2 * kp.PS : kp.N;
+    k_moments<D, PREC><<<nblk(count, 256), 256, 0, st>>>(
+        kp, (SP<PREC>)b.f[pc], (SP<PREC>)b.g[pc], (RP<PREC>)b.rho[fc], (RP<PREC>)b.phi[fc],
+        (RP<PREC>)b.rho[1 - fc], (RP<PREC>)b.phi[1 - fc]);
+    return LBM3_CHECK_LAUNCH();
+}
+
+int launch_moments(const KParams &kp, int prec, const Buffers &b, int pc, int fc, void *stream)
+{
+    hipStream_t st = (hipStream_t)stream;
+    if (kp.D == 2) {
+        if (prec == P64) return moments_t<2, P64>(kp, b, pc, fc, st);
+        if (prec == P32) return moments_t<2, P32>(kp, b, pc, fc, st);
+        return moments_t<2, P16>(kp, b, pc, fc, st);
+    }
+    if (prec == P64) return moments_t<3, P64>(kp, b, pc, fc, st);
+    if (prec == P32) return moments_t<3, P32>(kp, b, pc, fc, st);
+    return moments_t<3, P16>(kp, b, pc, fc, st);
+}
+
+int launch_ghost(const KParams &kp, int prec, const Buffers &b, int fdst, void *stream)
+{
+    if (!kp.walls) return 0;
+    hipStream_t st = (hipStream_t)stream;
+    long long np = kp.D == 2 ? kp.nx : (long long)kp.nx * kp.ny;
+    unsigned g = nblk(2 * np, 256);
+    if (prec == P64) {
+        if (kp.D == 2) k_ghost<2, double><<<g, 256, 0, st>>>(kp, (double *)b.rho[fdst], (double *)b.phi[fdst]);
+        else k_ghost<3, double><<<g, 256, 0, st>>>(kp, (double *)b.rho[fdst], (double *)b.phi[fdst]);
+    } else {
+        if (kp.D == 2) k_ghost<2, float><<<g, 256, 0, st>>>(kp, (float *)b.rho[fdst], (float *)b.phi[fdst]);
+        else k_ghost<3, float><<<g, 256, 0, st>>>(kp, (float *)b.rho[fdst], (float *)b.phi[fdst]);
+    }
+    return LBM3_CHECK_LAUNCH();
+}
+
+// chunk of march planes per block: enough blocks to fill the chip, at least
+// two planes so the ring prologue is amortised
+static int choose_chunk(long long tiles, int planes)
+{
+    const long long target = 2048;
+    long long c = (tiles * planes + target - 1) / target;
+    if (c < 2) c = 2;
+    if (c > 64) c = 64;
+    if (c > planes) c = planes;
+    return (int)c;
+}
+
+template <int D, int PREC, int TX, int TY>
+static int fused_t(const KParams &kp, const Buffers &b, int pc, int fc, hipStream_t st)
+{
+    int ntx = (kp.nx + TX - 1) / TX;
+    int nty = D == 3 ? (kp.ny + TY - 1) / TY : 1;
+    int planes = kp.walls ? kp.nw - 2 : kp.nw;
+    int chunk = choose_chunk((long long)ntx * nty, planes);
+    dim3 grid((unsigned)(ntx * nty), (unsigned)((planes + chunk - 1) / chunk));
+    k_fused<D, PREC, TX, TY><<<grid, TX * TY, 0, st>>>(
+        kp, (SP<PREC>)b.f[pc], (SP<PREC>)b.g[pc], (SP<PREC>)b.f[1 - pc], (SP<PREC>)b.g[1 - pc],
+        (RP<PREC>)b.rho[1 - fc], (RP<PREC>)b.phi[1 - fc], (RP<PREC>)b.rho[fc], (RP<PREC>)b.phi[fc],
+        b.counters, chunk);
+    return LBM3_CHECK_LAUNCH();
+}
+
+int launch_fused(const KParams &kp, int prec, const Buffers &b, int pc, int fc, void *stream)
+{
+    hipStream_t st = (hipStream_t)stream;
+    if (kp.D == 2) {
+        bool small = (long long)kp.nx * kp.nw < (1LL << 20);
+        if (prec == P64) return small ? fused_t<2, P64, 64, 1>(kp, b, pc, fc, st) : fused_t<2, P64, 256, 1>(kp, b, pc, fc, st);
+        if (prec == P32) return small ? fused_t<2, P32, 64, 1>(kp, b, pc, fc, st) : fused_t<2, P32, 256, 1>(kp, b, pc, fc, st);
+        return small ? fused_t<2, P16, 64, 1>(kp, b, pc, fc, st) : fused_t<2, P16, 256, 1>(kp, b, pc, fc, st);
+    }
+    if (prec == P64) return fused_t<3, P64, 32, 4>(kp, b, pc, fc, st);
+    if (prec == P32) return fused_t<3, P32, 32, 8>(kp, b, pc, fc, st);
+    return fused_t<3, P16, 32, 8>(kp, b, pc, fc, st);
+}
+
+template <int D, int PREC>
+static int init_t(const KParams &kp, const Buffers &b, hipStream_t st)
+{
+    long long count = kp.walls ? kp.N - 2 * kp.PS : kp.N;
+    k_init_pops<D, PREC><<<nblk(count, 256), 256, 0, st>>>(kp, (RP<PREC>)b.rho[0], (RP<PREC>)b.phi[0],
+                                                            (SP<PREC>)b.f[0], (SP<PREC>)b.g[0]);
+    return LBM3_CHECK_LAUNCH();
+}
+
+// upload staging -> fields: which = 0 rho, 1 phi (both field buffers)
+int launch_init_field(const KParams &kp, int prec, const Buffers &b, int which, void *stream)
+{
+    hipStream_t st = (hipStream_t)stream;
+    void **dst = which == 0 ? (void **)b.rho : (void **)b.phi;
+    if (prec == P64) k_init_fields<double><<<nblk(kp.N, 256), 256, 0, st>>>(kp.N, b.scratch, (double *)dst[0], (double *)dst[1]);
+    else k_init_fields<float><<<nblk(kp.N, 256), 256, 0, st>>>(kp.N, b.scratch, (float *)dst[0], (float *)dst[1]);
+    return LBM3_CHECK_LAUNCH();
+}
+
+int launch_init(const KParams &kp, int prec, const Buffers &b, void *stream)
+{
+    hipStream_t st = (hipStream_t)stream;
+    if (kp.D == 2) {
+        if (prec == P64) return init_t<2, P64>(kp, b, st);
+        if (prec == P32) return init_t<2, P32>(kp, b, st);
+        return init_t<2, P16>(kp, b, st);
+    }
+    if (prec == P64) return init_t<3, P64>(kp, b, st);
+    if (prec == P32) return init_t<3, P32>(kp, b, st);
+    return init_t<3, P16>(kp, b, st);
+}
+
+int observe_blocks(const KParams &kp)
+{
+    long long count = kp.walls ? kp.N - 2 * kp.PS : kp.N;
+    long long nb = (count + OBS_THREADS * 8 - 1) / (OBS_THREADS * 8);
+    if (nb < 1) nb = 1;
+    if (nb > 1024) nb = 1024;
+    return (int)nb;
+}
+
+template <int D, int PREC>
+static int observe_t(const KParams &kp, const Buffers &b, int pc, int fc, hipStream_t st)
+{
+    int nb = observe_blocks(kp);
+    k_observe<D, PREC><<<nb, OBS_THREADS, 0, st>>>(kp, (SP<PREC>)b.f[pc], (SP<PREC>)b.g[pc], (RP<PREC>)b.rho[fc],
+                                                    (RP<PREC>)b.phi[fc], b.partials);
+    k_reduce<<<1, NSUM, 0, st>>>(b.partials, nb, b.result);
+    return LBM3_CHECK_LAUNCH();
+}
+
+int launch_observe(const KParams &kp, int prec, const Buffers &b, int pc, int fc, void *stream)
+{
+    hipStream_t st = (hipStream_t)stream;
+    if (kp.D == 2) {
+        if (prec == P64) return observe_t<2, P64>(kp, b, pc, fc, st);
+        if (prec == P32) return observe_t<2, P32>(kp, b, pc, fc, st);
+        return observe_t<2, P16>(kp, b, pc, fc, st);
+    }
+    if (prec == P64) return observe_t<3, P64>(kp, b, pc, fc, st);
+    if (prec == P32) return observe_t<3, P32>(kp, b, pc, fc, st);
+    return observe_t<3, P16>(kp, b, pc, fc, st);
+}
+
+template <int D, int PREC>
+static int export_pop_t(const KParams &kp, const Buffers &b, int pc, int fc, int which, int i, hipStream_t st)
+{
+    const void *src = which == 0 ? b.f[pc] : b.g[pc];
+    k_export_pop<D, PREC><<<nblk(kp.N, 256), 256, 0, st>>>(kp.N, (const typename Ty<PREC>::S *)src, i,
+                                                           (RP<PREC>)b.rho[fc], (RP<PREC>)b.phi[fc], which,
+                                                           b.scratch);
+    return LBM3_CHECK_LAUNCH();
+}
+
+int launch_export_pop(const KParams &kp, int prec, const Buffers &b, int pc, int fc, int which, int i,
+                      void *stream)
+{
+    hipStream_t st = (hipStream_t)stream;
+    if (kp.D == 2) {
+        if (prec == P64) return export_pop_t<2, P64>(kp, b, pc, fc, which, i, st);
+        if (prec == P32) return export_pop_t<2, P32>(kp, b, pc, fc, which, i, st);
+        return export_pop_t<2, P16>(kp, b, pc, fc, which, i, st);
+    }
+    if (prec == P64) return export_pop_t<3, P64>(kp, b, pc, fc, which, i, st);
+    if (prec == P32) return export_pop_t<3, P32>(kp, b, pc, fc, which, i, st);
+    return export_pop_t<3, P16>(kp, b, pc, fc, which, i, st);
+}
+
+int launch_export_field(const KParams &kp, int prec, const Buffers &b, int fsrc, int which, void *stream)
+{
+    hipStream_t st = (hipStream_t)stream;
+    const void *src = which == 0 ? b.rho[fsrc] : b.phi[fsrc];
+    if (prec == P64) k_export_field<double><<<nblk(kp.N, 256), 256, 0, st>>>(kp.N, (const double *)src, b.scratch);
+    else k_export_field<float><<<nblk(kp.N, 256), 256, 0, st>>>(kp.N, (const float *)src, b.scratch);
+    return LBM3_CHECK_LAUNCH();
+}
+
+int launch_contour(const KParams &kp, int prec, const Buffers &b, int fsrc, int comp, int wall, double exclude,
+                   void *stream)
+{
+    hipStream_t st = (hipStream_t)stream;
+    long long nb = (kp.N + OBS_THREADS * 8 - 1) / (OBS_THREADS * 8);
+    if (nb > 1024) nb = 1024;
+    if (nb < 1) nb = 1;
+    if (prec == P64) {
+        if (kp.D == 2) k_contour<2, double><<<(unsigned)nb, OBS_THREADS, 0, st>>>(kp, (const double *)b.rho[fsrc], (const double *)b.phi[fsrc], comp, wall, exclude, b.partials);
+        else k_contour<3, double><<<(unsigned)nb, OBS_THREADS, 0, st>>>(kp, (const double *)b.rho[fsrc], (const double *)b.phi[fsrc], comp, wall, exclude, b.partials);
+    } else {
+        if (kp.D == 2) k_contour<2, float><<<(unsigned)nb, OBS_THREADS, 0, st>>>(kp, (const float *)b.rho[fsrc], (const float *)b.phi[fsrc], comp, wall, exclude, b.partials);
+        else k_contour<3, float><<<(unsigned)nb, OBS_THREADS, 0, st>>>(kp, (const float *)b.rho[fsrc], (const float *)b.phi[fsrc], comp, wall, exclude, b.partials);
+    }
+    k_reduce_sum<<<1, NSUM, 0, st>>>(b.partials, (int)nb, b.result);
+    return LBM3_CHECK_LAUNCH();
+}
+
+}  // namespace lbm3k

@@ -1,0 +1,256 @@
+"""ctypes binding of the lbm3 C ABI (include/lbm3.h).
+
+Argument marshalling only: every step of the update runs in the HIP library
+liblbm3.so.  PyTorch provides the device workspace (a uint8 tensor) and the
+stream.  Importing this module loads the library and fails loudly when it is
+missing; there is no CPU fallback.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbm3.so")
+
+D2Q9, D3Q27 = 9, 27
+WET_FORCE, WET_GEOM_INTERP, WET_GEOM_EXTRAP = 0, 1, 2
+FP64, FP32, FP16S = 0, 1, 2
+NO_COLLIDE, FORCE_ALPHA2 = 1, 2
+OBS_SUMS, OBS_FIELDS, OBS_POPS = 1, 2, 4
+STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EUNSTABLE", -4: "EDEVICE", -5: "ESTATE",
+          -6: "ECALIB"}
+
+
+class lbm3_params(C.Structure):
+    _fields_ = [
+        ("lattice", C.c_int32), ("n", C.c_int32 * 3), ("walls", C.c_int32),
+        ("rho_l", C.c_double), ("rho_g", C.c_double), ("native", C.c_int32),
+        ("lam", C.c_double * 3), ("kap", C.c_double * 3),
+        ("gamma12", C.c_double), ("gamma13", C.c_double), ("gamma23", C.c_double),
+        ("width", C.c_double), ("chi", C.c_double), ("tau_f", C.c_double),
+        ("tau_g", C.c_double), ("Gamma", C.c_double), ("wetting", C.c_int32),
+        ("theta_deg", (C.c_double * 3) * 2), ("kw", (C.c_double * 2) * 2),
+        ("precision", C.c_int32), ("flags", C.c_uint32), ("alpha_eps", C.c_double),
+        ("alpha_tol", C.c_double), ("alpha_maxit", C.c_int32),
+    ]
+
+
+class lbm3_derived(C.Structure):
+    _fields_ = [
+        ("a", C.c_double), ("b", C.c_double), ("T", C.c_double), ("C", C.c_double),
+        ("psi0", C.c_double), ("rho_l", C.c_double), ("rho_g", C.c_double),
+        ("lam", C.c_double * 3), ("kap", C.c_double * 3), ("kappa_rr", C.c_double),
+        ("kappa_pp", C.c_double), ("kappa_x", C.c_double), ("beta", C.c_double),
+        ("cot_theta", (C.c_double * 3) * 2),
+    ]
+
+
+class lbm3_obs(C.Structure):
+    _fields_ = [
+        ("mass", C.c_double * 3), ("rho_sum", C.c_double), ("phi_sum", C.c_double),
+        ("mom", C.c_double * 3), ("kinetic", C.c_double), ("umax", C.c_double),
+        ("n_bad", C.c_int64), ("n_newton", C.c_int64), ("n_shortcut", C.c_int64),
+        ("n_fallback", C.c_int64), ("step", C.c_int64),
+    ]
+
+
+EXPORTS = ["lbm3_footprint", "lbm3_resolve", "lbm3_create", "lbm3_init", "lbm3_step",
+           "lbm3_observe", "lbm3_contact_angle", "lbm3_destroy", "lbm3_last_error"]
+
+
+class Lbm3Error(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("lbm3 %s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """The loaded HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("liblbm3.so not built: run __graft_entry__.build() or "
+                              "python paper_1904_06881_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        vp, dp = C.c_void_p, C.POINTER(C.c_double)
+        L.lbm3_footprint.restype = C.c_size_t
+        L.lbm3_footprint.argtypes = [C.POINTER(lbm3_params)]
+        L.lbm3_resolve.restype = C.c_int
+        L.lbm3_resolve.argtypes = [C.POINTER(lbm3_params), C.POINTER(lbm3_derived)]
+        L.lbm3_create.restype = C.c_int
+        L.lbm3_create.argtypes = [C.POINTER(lbm3_params), vp, C.c_size_t, vp, C.POINTER(vp)]
+        L.lbm3_init.restype = C.c_int
+        L.lbm3_init.argtypes = [vp, dp, dp]
+        L.lbm3_step.restype = C.c_int
+        L.lbm3_step.argtypes = [vp, C.c_int64]
+        L.lbm3_observe.restype = C.c_int
+        L.lbm3_observe.argtypes = [vp, C.c_uint32, C.POINTER(lbm3_obs), dp, dp, dp, dp]
+        L.lbm3_contact_angle.restype = C.c_int
+        L.lbm3_contact_angle.argtypes = [vp, C.c_int32, C.c_int32, C.c_double, dp]
+        L.lbm3_destroy.restype = C.c_int
+        L.lbm3_destroy.argtypes = [vp]
+        L.lbm3_last_error.restype = C.c_char_p
+        L.lbm3_last_error.argtypes = [vp]
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def make_params(lattice, n, *, walls=True, rho_l=1.0, rho_g=1e-3, lam=None, kap=None,
+                gamma=None, width=4.0, chi=5.0, tau_f=1.0, tau_g=1.0, Gamma=1.0,
+                wetting=WET_GEOM_INTERP, theta_deg=90.0, kw=((0, 0), (0, 0)), precision=FP64,
+                flags=0, alpha_eps=0.0, alpha_tol=0.0, alpha_maxit=0):
+    """Fill lbm3_params.  Give lam/kap (native) or gamma=(g12, g13, g23) with
+    width.  theta_deg: scalar, (theta21, theta31, theta23) or a 2x3 table."""
+    p = lbm3_params()
+    p.lattice = lattice
+    nn = list(n) + [1] * (3 - len(n))
+    for k in range(3):
+        p.n[k] = int(nn[k])
+    p.walls = 1 if walls else 0
+    p.rho_l, p.rho_g = rho_l, rho_g
+    if lam is not None:
+        p.native = 1
+        for k in range(3):
+            p.lam[k], p.kap[k] = lam[k], kap[k]
+    else:
+        p.native = 0
+        p.gamma12, p.gamma13, p.gamma23 = gamma
+        p.width = width
+    p.chi, p.tau_f, p.tau_g, p.Gamma = chi, tau_f, tau_g, Gamma
+    p.wetting = wetting
+    th = np.asarray(theta_deg, dtype=np.float64)
+    if th.ndim == 0:
+        th = np.full((2, 3), float(th))
+    elif th.ndim == 1:
+        th = np.stack([th, th])
+    for w in range(2):
+        for k in range(3):
+            p.theta_deg[w][k] = float(th[w][k])
+        for k in range(2):
+            p.kw[w][k] = float(kw[w][k])
+    p.precision = precision
+    p.flags = flags
+    p.alpha_eps, p.alpha_tol, p.alpha_maxit = alpha_eps, alpha_tol, alpha_maxit
+    return p
+
+
+def lbm3_footprint(p):
+    return lib().lbm3_footprint(C.byref(p))
+
+
+def lbm3_resolve(p):
+    d = lbm3_derived()
+    st = lib().lbm3_resolve(C.byref(p), C.byref(d))
+    if st != 0:
+        raise Lbm3Error(st, "parameter resolution failed")
+    return d
+
+
+def lbm3_create(p, workspace_ptr, nbytes, stream_ptr):
+    h = C.c_void_p()
+    st = lib().lbm3_create(C.byref(p), C.c_void_p(workspace_ptr), nbytes, C.c_void_p(stream_ptr),
+                           C.byref(h))
+    if st != 0:
+        raise Lbm3Error(st, lib().lbm3_last_error(None).decode())
+    return h
+
+
+def _check(h, st):
+    if st != 0:
+        raise Lbm3Error(st, lib().lbm3_last_error(h).decode())
+
+
+def lbm3_init(h, rho0, phi0):
+    r = np.ascontiguousarray(rho0, dtype=np.float64).reshape(-1)
+    ph = np.ascontiguousarray(phi0, dtype=np.float64).reshape(-1)
+    _check(h, lib().lbm3_init(h, _dp(r), _dp(ph)))
+
+
+def lbm3_step(h, nsteps):
+    _check(h, lib().lbm3_step(h, int(nsteps)))
+
+
+def lbm3_observe(h, what, rho_out=None, phi_out=None, f_out=None, g_out=None, check=True):
+    o = lbm3_obs()
+    st = lib().lbm3_observe(h, what, C.byref(o), _dp(rho_out), _dp(phi_out), _dp(f_out), _dp(g_out))
+    if check and st not in (0, -3):
+        _check(h, st)
+    return st, o
+
+
+def lbm3_contact_angle(h, comp, wall, exclude):
+    out = np.zeros(6)
+    _check(h, lib().lbm3_contact_angle(h, comp, wall, exclude, _dp(out)))
+    return out
+
+
+def lbm3_destroy(h):
+    return lib().lbm3_destroy(h)
+
+
+class Sim:
+    """One simulation on a CUDA (HIP) device: owns a torch workspace and uses
+    the current torch stream.  Arrays are (ny, nx) or (nz, ny, nx)."""
+
+    def __init__(self, p, device="cuda:0", stream=None):
+        import torch
+        self.p = p
+        self.D = 2 if p.lattice == D2Q9 else 3
+        self.Q = p.lattice
+        self.shape = (p.n[1], p.n[0]) if self.D == 2 else (p.n[2], p.n[1], p.n[0])
+        self.N = int(np.prod(self.shape))
+        nbytes = lbm3_footprint(p)
+        if nbytes == 0:
+            raise Lbm3Error(-1, "invalid parameters")
+        self.device = torch.device(device)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.h = lbm3_create(p, self.ws.data_ptr(), nbytes, self.stream.cuda_stream)
+        self.derived = lbm3_resolve(p)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lbm3_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init(self, rho0, phi0):
+        lbm3_init(self.h, rho0, phi0)
+
+    def step(self, n=1):
+        lbm3_step(self.h, n)
+
+    def observe(self):
+        st, o = lbm3_observe(self.h, OBS_SUMS)
+        return {"mass": list(o.mass), "rho_sum": o.rho_sum, "phi_sum": o.phi_sum,
+                "mom": list(o.mom), "kinetic": o.kinetic, "umax": o.umax, "n_bad": o.n_bad,
+                "n_newton": o.n_newton, "n_shortcut": o.n_shortcut, "n_fallback": o.n_fallback,
+                "step": o.step, "status": st}
+
+    def fields(self):
+        r = np.empty(self.N)
+        ph = np.empty(self.N)
+        lbm3_observe(self.h, OBS_FIELDS, rho_out=r, phi_out=ph)
+        return r.reshape(self.shape), ph.reshape(self.shape)
+
+    def pops(self):
+        f = np.empty(self.Q * self.N)
+        g = np.empty(self.Q * self.N)
+        lbm3_observe(self.h, OBS_POPS, f_out=f, g_out=g)
+        return f.reshape((self.Q,) + self.shape), g.reshape((self.Q,) + self.shape)
+
+    def contact_angle(self, comp=2, wall=0, exclude=8.0):
+        return lbm3_contact_angle(self.h, comp, wall, exclude)

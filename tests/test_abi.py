@@ -1,0 +1,105 @@
+"""The C ABI library loads, exports what include/lbm3.h declares, validates
+parameters and resolves the thermodynamics on the host (no GPU calls)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1904_06881_amd import lbm3 as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "lbm3.h")).read()
+    decl = r"^\s*(?:size_t|lbm3_status|const\s+char\s*\*)\s*(lbm3_[a-z_]+)\s*\("
+    return sorted(set(re.findall(decl, src, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.lib()
+    names = declared_symbols()
+    assert len(names) >= 9
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(L.EXPORTS)
+
+
+def test_footprint_and_validation():
+    p = L.make_params(L.D2Q9, (128, 64), lam=(0.07, 0.03, 0.03), kap=(0.03, 0.03, 0.03))
+    fp = L.lbm3_footprint(p)
+    N = 128 * 64
+    assert fp >= 2 * 2 * 9 * N * 8 + 4 * N * 8 + N * 8
+    p32 = L.make_params(L.D2Q9, (128, 64), lam=(0.07, 0.03, 0.03), kap=(0.03, 0.03, 0.03), precision=L.FP32)
+    p16 = L.make_params(L.D2Q9, (128, 64), lam=(0.07, 0.03, 0.03), kap=(0.03, 0.03, 0.03), precision=L.FP16S)
+    assert L.lbm3_footprint(p16) < L.lbm3_footprint(p32) < fp
+    bad = [
+        L.make_params(7, (8, 8), lam=(1, 1, 1), kap=(1, 1, 1)),
+        L.make_params(L.D2Q9, (8, 2), lam=(1, 1, 1), kap=(1, 1, 1)),
+        L.make_params(L.D2Q9, (8, 8), rho_l=0.001, rho_g=1.0, lam=(1, 1, 1), kap=(1, 1, 1)),
+        L.make_params(L.D2Q9, (8, 8), tau_f=0.5, lam=(1, 1, 1), kap=(1, 1, 1)),
+        L.make_params(L.D2Q9, (8, 8), theta_deg=10.0, lam=(1, 1, 1), kap=(1, 1, 1)),
+    ]
+    for b in bad:
+        assert L.lbm3_footprint(b) == 0
+
+
+def test_create_rejects_small_workspace_without_device():
+    p = L.make_params(L.D2Q9, (16, 8), lam=(0.07, 0.03, 0.03), kap=(0.03, 0.03, 0.03))
+    with pytest.raises(L.Lbm3Error) as e:
+        L.lbm3_create(p, 0, 0, 0)
+    assert e.value.status == -2
+
+
+@pytest.mark.parametrize("ratio,rho_l", [(1000.0, 1.0), (100.0, 1.0), (10.0, 2.0), (3.0, 1.0)])
+def test_resolve_coexistence_matches_oracle(ratio, rho_l):
+    """Host coexistence (Newton continuation) equals the oracle's nested
+    bisection."""
+    p = L.make_params(L.D2Q9, (8, 8), rho_l=rho_l, rho_g=rho_l / ratio, lam=(0.1, 0.1, 0.1),
+                      kap=(0.1, 0.1, 0.1))
+    d = L.lbm3_resolve(p)
+    e = O.coexistence(ratio, rho_l)
+    for k in ["a", "b", "T", "C", "psi0", "rho_l", "rho_g"]:
+        assert abs(getattr(d, k) - e[k]) <= 1e-10 * abs(e[k]), k
+    assert d.beta == 0.5
+
+
+def test_resolve_cot_special_angles():
+    p = L.make_params(L.D2Q9, (8, 8), lam=(0.1, 0.1, 0.1), kap=(0.1, 0.1, 0.1),
+                      theta_deg=[[45.0, 90.0, 135.0], [60.0, 26.56505117707799, 120.0]])
+    d = L.lbm3_resolve(p)
+    assert d.cot_theta[0][0] == 1.0 and d.cot_theta[0][1] == 0.0 and d.cot_theta[0][2] == -1.0
+    assert d.cot_theta[1][1] == 2.0
+    assert abs(d.cot_theta[1][0] - 1 / np.sqrt(3)) < 1e-15
+
+
+@pytest.mark.parametrize("gam", [(0.01, 0.01, 0.01), (0.02, 0.015, 0.01)])
+def test_calibration_meets_targets_on_oracle(gam):
+    """(gamma, width) -> (lambda, kappa): the resolved parameters, relaxed as
+    flat interfaces by the oracle's own gradient flow, give the target liquid-
+    gas tensions and the mean 10-90 % width 2 alpha23 ln 9 (alpha23 = W/4);
+    gamma23 follows Eq. 38 and kappa_i = alpha23^2 lambda_i (Eq. 36)."""
+    W = 4.0
+    p = L.make_params(L.D2Q9, (8, 8), gamma=gam, width=W)
+    d = L.lbm3_resolve(p)
+    a23 = W / 4
+    assert abs(d.lam[1] + d.lam[2] - 6 * gam[2] / a23) < 1e-12
+    for k in (1, 2):
+        assert abs(d.kap[k] - a23 ** 2 * d.lam[k]) < 1e-14
+    eos = O.coexistence(1000.0, 1.0)
+    po = O.make_params(2, (8, 8), walls=False, lam=list(d.lam), kap=list(d.kap), eos=eos)
+    g12, w12 = O.flat_tension(po, 12, n=64)
+    g13, w13 = O.flat_tension(po, 13, n=64)
+    assert abs(g12 - gam[0]) < 1e-6 * gam[0]
+    assert abs(g13 - gam[1]) < 1e-6 * gam[1]
+    assert abs(0.5 * (w12 + w13) - 2 * a23 * np.log(9.0)) < 1e-6
+
+
+def test_calibration_rejects_impossible_tensions():
+    p = L.make_params(L.D2Q9, (8, 8), gamma=(0.005, 0.03, 0.02), width=4.0)
+    with pytest.raises(L.Lbm3Error) as e:
+        L.lbm3_resolve(p)
+    assert e.value.status == -6

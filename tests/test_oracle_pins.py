@@ -528,3 +528,25 @@ def test_kasa_fit_exact_on_circle():
         C2 = 0.5 * (1 + ph / 5.0 - (r - 1.0) / (1e-3 - 1.0))
         got, _ = O.contact_angle_2d(C2, wall_y=0.5)
         assert abs(got - th) < 0.3, (th, got)
+
+
+def test_alpha_small_deviation_root():
+    """Below the shortcut threshold alpha is the expansion of the entropy
+    equation about alpha = 2; it agrees with the Newton root of the same
+    equation to second order in the deviation, and both satisfy the entropy
+    equation written with the definition of H (Eq. 32)."""
+    c, w = O.lattice(2)
+    for scale in (3e-3, 1e-3, 3e-4):
+        for _ in range(10):
+            rho = rng.uniform(0.1, 1.0)
+            f = O.feq(2, rho, rng.uniform(-0.05, 0.05, 2)) * (1 + scale * rng.uniform(-1, 1, 9))
+            r2 = f.sum()
+            fd = O.feq(2, r2, (f @ c) / r2)
+            delta = fd - f
+            x = delta / f
+            a_ser, k0 = O.alpha(f, delta, eps=1.0)
+            a_nwt, k1 = O.alpha(f, delta, eps=0.0, tol=1e-11, maxit=50)
+            assert k0 == 0 and k1 == 1
+            assert abs(a_ser - a_nwt) < 30 * np.abs(x).max() ** 2
+            h0 = _H(f, w)
+            assert abs(_H(f + a_nwt * delta, w) - h0) < 1e-13 * abs(h0) + 1e-15
