@@ -91,7 +91,8 @@ typedef struct {
                                populations stored in FP16 as density-scaled
                                offsets from the lattice weights) */
     uint32_t flags;         /* LBM3_NO_COLLIDE | LBM3_FORCE_ALPHA2 */
-    double  alpha_eps;      /* alpha = 2 below this deviation (0: 1e-3) */
+    double  alpha_eps;      /* small-deviation alpha below this max |Delta/f'|
+                               (0: 1e-3 FP64, 1e-2 FP32 arithmetic) */
     double  alpha_tol;      /* Newton tolerance (0: 1e-10 FP64, 1e-5 FP32) */
     int32_t alpha_maxit;    /* Newton iteration cap (0: 20) */
 } lbm3_params;
@@ -142,6 +143,13 @@ lbm3_status lbm3_init(lbm3 *h, const double *rho0, const double *phi0);
 
 /* Enqueue nsteps full updates on the handle's stream (asynchronous). */
 lbm3_status lbm3_step(lbm3 *h, int64_t nsteps);
+
+/* As lbm3_step, with a HIP event recorded around every launch on the
+ * handle's stream; synchronises.  kernel_ms[0..2] (host, may be NULL) receive
+ * the summed device time of the moments, ghost-layer and fused
+ * (stencil + collision + streaming) kernels over the nsteps steps, and
+ * kernel_ms[3] the time from the first to the last event. */
+lbm3_status lbm3_step_profiled(lbm3 *h, int64_t nsteps, double *kernel_ms);
 
 /* Synchronise the stream and report the current state.  what: LBM3_OBS_*
  * bits.  out may be NULL unless LBM3_OBS_SUMS is set.  rho_out/phi_out

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <new>
 #include <string>
 #include <vector>
@@ -207,7 +208,9 @@ lbm3_status lbm3_create(const lbm3_params *p, void *ws, size_t bytes, void *stre
         for (int c = 0; c < 3; ++c) k.cot[w][c] = d.cot_theta[w][c];
         for (int c = 0; c < 2; ++c) k.kw[w][c] = p->kw[w][c];
     }
-    k.alpha_eps = p->alpha_eps > 0 ? p->alpha_eps : 1e-3;
+    // below this deviation alpha comes from the expansion of the entropy
+    // equation; FP32 keeps Newton to deviations where its root is resolved
+    k.alpha_eps = p->alpha_eps > 0 ? p->alpha_eps : (p->precision == LBM3_FP64 ? 1e-3 : 1e-2);
     k.alpha_tol = p->alpha_tol > 0 ? p->alpha_tol : (p->precision == LBM3_FP64 ? 1e-10 : 1e-5);
     k.alpha_maxit = p->alpha_maxit > 0 ? p->alpha_maxit : 20;
     k.flags = p->flags;
@@ -244,6 +247,13 @@ lbm3_status lbm3_init(lbm3 *h, const double *rho0, const double *phi0)
             return set_err(h, LBM3_EINVAL, "initial rho must be positive and finite on fluid nodes");
     }
     hipError_t e;
+    // populations of the ghost layers are never read by a step; zeroing both
+    // buffers keeps exported arrays deterministic
+    size_t pop_bytes = (size_t)k.Q * k.N * (h->prec == LBM3_FP64 ? 8 : (h->prec == LBM3_FP32 ? 4 : 2));
+    for (int i = 0; i < 2; ++i)
+        if ((e = hipMemsetAsync(h->b.f[i], 0, pop_bytes, h->stream)) != hipSuccess ||
+            (e = hipMemsetAsync(h->b.g[i], 0, pop_bytes, h->stream)) != hipSuccess)
+            return hip_err(h, e, "clear populations");
     const double *src[2] = {rho0, phi0};
     for (int which = 0; which < 2; ++which) {
         if ((e = hipMemcpyAsync(h->b.scratch, src[which], bytes, hipMemcpyHostToDevice, h->stream)) != hipSuccess)
@@ -277,6 +287,62 @@ lbm3_status lbm3_step(lbm3 *h, int64_t nsteps)
         h->step++;
     }
     return LBM3_OK;
+}
+
+lbm3_status lbm3_step_profiled(lbm3 *h, int64_t nsteps, double *kernel_ms)
+{
+    if (!h) return LBM3_EINVAL;
+    if (!h->inited) return set_err(h, LBM3_ESTATE, "step before init");
+    if (nsteps < 0) return set_err(h, LBM3_EINVAL, "negative step count");
+    const KParams &k = h->kp;
+    const int batch = 128;
+    std::vector<hipEvent_t> ev(4 * batch);
+    hipError_t e = hipSuccess;
+    for (auto &x : ev)
+        if ((e = hipEventCreate(&x)) != hipSuccess) return hip_err(h, e, "event create");
+    double acc[3] = {0, 0, 0}, span = 0;
+    hipEvent_t first = nullptr, last = nullptr;
+    hipEventCreate(&first);
+    hipEventCreate(&last);
+    hipEventRecord(first, h->stream);
+    lbm3_status st = LBM3_OK;
+    for (int64_t t0 = 0; t0 < nsteps && st == LBM3_OK; t0 += batch) {
+        int nb = (int)std::min<int64_t>(batch, nsteps - t0);
+        for (int s = 0; s < nb; ++s) {
+            hipEventRecord(ev[4 * s], h->stream);
+            int r1 = lbm3k::launch_moments(k, h->prec, h->b, h->pc, h->fc, h->stream);
+            hipEventRecord(ev[4 * s + 1], h->stream);
+            int r2 = lbm3k::launch_ghost(k, h->prec, h->b, 1 - h->fc, h->stream);
+            hipEventRecord(ev[4 * s + 2], h->stream);
+            int r3 = lbm3k::launch_fused(k, h->prec, h->b, h->pc, h->fc, h->stream);
+            hipEventRecord(ev[4 * s + 3], h->stream);
+            if (r1 || r2 || r3) { st = set_err(h, LBM3_EDEVICE, "kernel launch failed"); break; }
+            h->pc ^= 1;
+            h->fc ^= 1;
+            h->step++;
+        }
+        if ((e = hipEventSynchronize(ev[4 * nb - 1])) != hipSuccess) { st = hip_err(h, e, "profiled step"); break; }
+        for (int s = 0; s < nb; ++s)
+            for (int j = 0; j < 3; ++j) {
+                float ms = 0;
+                hipEventElapsedTime(&ms, ev[4 * s + j], ev[4 * s + j + 1]);
+                acc[j] += ms;
+            }
+    }
+    hipEventRecord(last, h->stream);
+    if (hipEventSynchronize(last) == hipSuccess) {
+        float ms = 0;
+        hipEventElapsedTime(&ms, first, last);
+        span = ms;
+    }
+    for (auto &x : ev) hipEventDestroy(x);
+    hipEventDestroy(first);
+    hipEventDestroy(last);
+    if (kernel_ms) {
+        for (int j = 0; j < 3; ++j) kernel_ms[j] = acc[j];
+        kernel_ms[3] = span;
+    }
+    return st;
 }
 
 lbm3_status lbm3_observe(lbm3 *h, uint32_t what, lbm3_obs *out, double *rho_out, double *phi_out, double *f_out,

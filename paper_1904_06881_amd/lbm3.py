@@ -56,7 +56,8 @@ class lbm3_obs(C.Structure):
 
 
 EXPORTS = ["lbm3_footprint", "lbm3_resolve", "lbm3_create", "lbm3_init", "lbm3_step",
-           "lbm3_observe", "lbm3_contact_angle", "lbm3_destroy", "lbm3_last_error"]
+           "lbm3_step_profiled", "lbm3_observe", "lbm3_contact_angle", "lbm3_destroy",
+           "lbm3_last_error"]
 
 
 class Lbm3Error(RuntimeError):
@@ -87,6 +88,8 @@ def lib():
         L.lbm3_init.argtypes = [vp, dp, dp]
         L.lbm3_step.restype = C.c_int
         L.lbm3_step.argtypes = [vp, C.c_int64]
+        L.lbm3_step_profiled.restype = C.c_int
+        L.lbm3_step_profiled.argtypes = [vp, C.c_int64, dp]
         L.lbm3_observe.restype = C.c_int
         L.lbm3_observe.argtypes = [vp, C.c_uint32, C.POINTER(lbm3_obs), dp, dp, dp, dp]
         L.lbm3_contact_angle.restype = C.c_int
@@ -178,6 +181,14 @@ def lbm3_step(h, nsteps):
     _check(h, lib().lbm3_step(h, int(nsteps)))
 
 
+def lbm3_step_profiled(h, nsteps):
+    """Run nsteps with events around every launch; returns device ms summed
+    per kernel (moments, ghost, fused) and the span of the whole run."""
+    ms = np.zeros(4)
+    _check(h, lib().lbm3_step_profiled(h, int(nsteps), _dp(ms)))
+    return {"moments": ms[0], "ghost": ms[1], "fused": ms[2], "span": ms[3]}
+
+
 def lbm3_observe(h, what, rho_out=None, phi_out=None, f_out=None, g_out=None, check=True):
     o = lbm3_obs()
     st = lib().lbm3_observe(h, what, C.byref(o), _dp(rho_out), _dp(phi_out), _dp(f_out), _dp(g_out))
@@ -232,6 +243,9 @@ class Sim:
 
     def step(self, n=1):
         lbm3_step(self.h, n)
+
+    def step_profiled(self, n):
+        return lbm3_step_profiled(self.h, n)
 
     def observe(self):
         st, o = lbm3_observe(self.h, OBS_SUMS)

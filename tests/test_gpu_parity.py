@@ -167,7 +167,8 @@ def test_force_kw0_equals_geometric90_gpu():
         s.init(rho0, phi0)
         s.step(30)
         out.append(s.pops())
-    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    fl = (slice(None), slice(1, -1))
+    assert np.array_equal(out[0][0][fl], out[1][0][fl]) and np.array_equal(out[0][1][fl], out[1][1][fl])
 
 
 # ------------------------------------------------------ precision forms ---
@@ -183,17 +184,23 @@ def test_reduced_precision_2000_steps_cfg1(prec, tol):
 
 
 def test_mass_conservation_gpu_fp64():
+    """Collision and bounce-back conserve sum rho and sum phi, hence the
+    component masses (affine in both): relative drift <= 1e-12 over 2000 steps
+    (the rounding of the update itself drifts ~1e-13)."""
     rho0, phi0 = I.sessile_drop_2d(128, 64, 20, xc=64)
     p = cfg1_params()
     say("mass fp64")
     s = L.Sim(p)
     s.init(rho0, phi0)
     o0 = s.observe()
-    s.step(500)
+    s.step(2000)
     o = s.observe()
-    nF = 128 * 62
+    d = s.derived
+    assert abs(o["rho_sum"] - o0["rho_sum"]) <= 1e-12 * o0["rho_sum"]
+    assert abs(o["phi_sum"] - o0["phi_sum"]) <= 1e-12 * abs(o0["phi_sum"])
+    scale = o0["rho_sum"] / (d.rho_l - d.rho_g) + abs(o0["phi_sum"]) / 5.0
     for k in range(3):
-        assert abs(o["mass"][k] - o0["mass"][k]) <= 1e-12 * max(abs(o0["mass"][k]), 1e-3 * nF)
+        assert abs(o["mass"][k] - o0["mass"][k]) <= 1e-12 * max(abs(o0["mass"][k]), scale)
     assert o["n_bad"] == 0
 
 
