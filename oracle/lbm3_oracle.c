@@ -325,8 +325,10 @@ void or_local_thermo(const or_params *p, double rho, double phi,
  *   - otherwise Newton from min(2, (1 + alpha_max)/2), alpha_max =
  *     min_{Delta_i<0} -f'_i/Delta_i the positivity limit; an iterate that
  *     leaves (1, alpha_max) is replaced by the midpoint towards the violated
- *     bound; stop when |step| < tol; no convergence within maxit (or a
- *     non-positive slope) -> alpha = min(2, alpha_max) (fallback). */
+ *     bound; stop when |step| < tol, or when a step below 10 tol fails to
+ *     halve the previous one (the root is resolved to rounding); no
+ *     convergence within maxit (or a non-positive slope) ->
+ *     alpha = min(2, alpha_max) (fallback). */
 int or_alpha(int Q, const double *w, const double *fp, const double *delta,
              double eps, double tol, int maxit, double *alpha)
 {
@@ -357,6 +359,7 @@ int or_alpha(int Q, const double *w, const double *fp, const double *delta,
         if (delta[i] < 0.0 && -fp[i] / delta[i] < amax) amax = -fp[i] / delta[i];
     for (int i = 0; i < Q; ++i) l1x[i] = log1p(x[i]);
     double a = (2.0 < amax) ? 2.0 : 0.5 * (1.0 + amax);
+    double prev = INFINITY;
     for (int it = 0; it < maxit; ++it) {
         double G = 0.0, dG = 0.0;
         for (int i = 0; i < Q; ++i) {
@@ -368,7 +371,9 @@ int or_alpha(int Q, const double *w, const double *fp, const double *delta,
         double an = a - G / dG;
         if (an >= amax) an = 0.5 * (a + amax);
         if (an <= 1.0) an = 0.5 * (a + 1.0);
-        if (fabs(an - a) < tol) { *alpha = an; return 1; }
+        double st = fabs(an - a);
+        if (st < tol || (st < 10.0 * tol && st > 0.5 * prev)) { *alpha = an; return 1; }
+        prev = st;
         a = an;
     }
     *alpha = (2.0 < amax) ? 2.0 : amax;

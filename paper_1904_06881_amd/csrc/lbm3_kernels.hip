@@ -194,7 +194,8 @@ __device__ __forceinline__ void feq(R rho, const R *u, R *fe)
 // from the expansion of G about alpha = 2: 2 + (S3 - 2 S4)/(3 S2 - 4 S3),
 // S_k = sum f' x^k), 1 Newton root, 2 fallback (non-positive f' or no
 // convergence).  Iterates are kept in (1, alpha_max), alpha_max = min_{x<0}
-// -1/x the positivity limit.  On return dx holds x (is_x = true) or, after a
+// -1/x the positivity limit; iteration stops when |step| < tol or when a step
+// below 10 tol fails to halve the previous one (resolved to rounding).  On return dx holds x (is_x = true) or, after a
 // non-positive f', still Delta.
 template <int Q, typename R>
 __device__ __forceinline__ R entropic_alpha(const R *fp, R *dx, R eps, R tol, int maxit, int &kind,
@@ -229,6 +230,8 @@ __device__ __forceinline__ R entropic_alpha(const R *fp, R *dx, R eps, R tol, in
 #pragma unroll
     for (int i = 0; i < Q; ++i) l1[i] = log1p(dx[i]);
     R al = ((R)2 < amax) ? (R)2 : (R)0.5 * ((R)1 + amax);
+    const R stag = (R)10 * tol;
+    R prev = (R)INFINITY;
     for (int it = 0; it < maxit; ++it) {
         R G = 0, dG = 0;
 #pragma unroll
@@ -242,7 +245,9 @@ __device__ __forceinline__ R entropic_alpha(const R *fp, R *dx, R eps, R tol, in
         R an = al - G / dG;
         if (an >= amax) an = (R)0.5 * (al + amax);
         if (an <= (R)1) an = (R)0.5 * (al + (R)1);
-        if (fabs(an - al) < tol) { kind = 1; return an; }
+        R st = fabs(an - al);
+        if (st < tol || (st < stag && st > (R)0.5 * prev)) { kind = 1; return an; }
+        prev = st;
         al = an;
     }
     kind = 2;
