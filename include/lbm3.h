@@ -68,7 +68,8 @@ enum {
 /* Problem statement (paper Sec. II-IV).  Zero-initialise, then set. */
 typedef struct {
     int32_t lattice;        /* LBM3_D2Q9 or LBM3_D3Q27 */
-    int32_t n[3];           /* nx, ny, nz (nz = 1 for D2Q9); >= 3 on the wall axis */
+    int32_t n[3];           /* nx, ny, nz (nz = 1 for D2Q9); >= 3 on the wall axis;
+                               nx ny nz < 2^32 (else LBM3_EINVAL) */
     int32_t walls;          /* 1: walls at both ends of the last axis; 0: periodic */
     double  rho_l, rho_g;   /* coexistence densities (Carnahan-Starling, Sec. II A):
                                the temperature follows from rho_l/rho_g at the

@@ -54,7 +54,8 @@ bool validate(const lbm3_params *p, std::string &why)
     if (D == 2 && p->n[2] > 1) { why = "n[2] must be 1 for D2Q9"; return false; }
     int nw = D == 2 ? p->n[1] : nz;
     if (p->walls && nw < 3) { why = "the wall axis needs at least 3 layers"; return false; }
-    if ((long long)p->n[0] * p->n[1] * nz > (1LL << 34)) { why = "grid too large"; return false; }
+    // node offsets inside one population array are 32-bit in the kernels
+    if ((long long)p->n[0] * p->n[1] * nz >= (1LL << 32)) { why = "grid too large (2^32 nodes or more)"; return false; }
     if (!(p->rho_l > 0.0) || !(p->rho_g > 0.0) || !(p->rho_l > p->rho_g)) {
         why = "need rho_l > rho_g > 0";
         return false;

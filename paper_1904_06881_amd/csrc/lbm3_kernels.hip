@@ -163,21 +163,26 @@ template <typename R> __device__ __forceinline__ R link_p(R rx, R ry)
 }
 
 // ------------------------------------------------------------ equilibria -
-// f_i^eq = rho w_i prod_a A(u_a) B(u_a)^{c_ia}, Eqs. 25-27.
+// f_i^eq = rho w_i prod_a A(u_a) B(u_a)^{c_ia}, Eqs. 25-27, from per-axis
+// factors fac[a][c+1] = w1(c) A(u_a) B(u_a)^c: f^eq_i = rho prod_a fac[a][c_ia + 1].
+template <typename R>
+__device__ __forceinline__ void feq_factors(R u, R *fac)
+{
+    R s = sqrt((R)1 + (R)3 * u * u);
+    R A = (R)2 - s;
+    R B = ((R)2 * u + s) / ((R)1 - u);
+    fac[0] = (R)(1.0 / 6.0) * A / B;
+    fac[1] = (R)(2.0 / 3.0) * A;
+    fac[2] = (R)(1.0 / 6.0) * A * B;
+}
+
 template <int D, typename R>
 __device__ __forceinline__ void feq(R rho, const R *u, R *fe)
 {
     constexpr int Q = D == 2 ? 9 : 27;
     R fac[3][3];
 #pragma unroll
-    for (int a = 0; a < D; ++a) {
-        R s = sqrt((R)1 + (R)3 * u[a] * u[a]);
-        R A = (R)2 - s;
-        R B = ((R)2 * u[a] + s) / ((R)1 - u[a]);
-        fac[a][0] = (R)(1.0 / 6.0) * A / B;
-        fac[a][1] = (R)(2.0 / 3.0) * A;
-        fac[a][2] = (R)(1.0 / 6.0) * A * B;
-    }
+    for (int a = 0; a < D; ++a) feq_factors(u[a], fac[a]);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         R v = rho * fac[0][cdir(D, i, 0) + 1] * fac[1][cdir(D, i, 1) + 1];
@@ -398,8 +403,19 @@ k_ghost(KParams kp, R *__restrict__ rho, R *__restrict__ phi)
 }
 
 // ---------------------------------------------------------------- fused --
+// wrap of v into [0, n) for |v| < 2n (one conditional each way)
+__device__ __forceinline__ int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+// general wrap without a division (setup only)
+__device__ __forceinline__ int wrapl(int v, int n)
+{
+    while (v < 0) v += n;
+    while (v >= n) v -= n;
+    return v;
+}
+
 template <int D, int PREC, int TX, int TY>
 __global__ void __launch_bounds__(TX * TY)
+__attribute__((amdgpu_waves_per_eu(D == 3 ? (PREC == P64 ? 1 : 2) : (PREC == P64 ? 2 : 4))))
 k_fused(KParams kp, const typename Ty<PREC>::S *__restrict__ fin, const typename Ty<PREC>::S *__restrict__ gin,
         typename Ty<PREC>::S *__restrict__ fout, typename Ty<PREC>::S *__restrict__ gout,
         const typename Ty<PREC>::R *__restrict__ rho, const typename Ty<PREC>::R *__restrict__ phi,
@@ -407,12 +423,15 @@ k_fused(KParams kp, const typename Ty<PREC>::S *__restrict__ fin, const typename
         unsigned long long *__restrict__ cnt, int chunk)
 {
     using R = typename Ty<PREC>::R;
+    using S = typename Ty<PREC>::S;
     constexpr int Q = D == 2 ? 9 : 27;
     constexpr int NTH = TX * TY;
     constexpr int FW = TX + 4, FH = D == 3 ? TY + 4 : 1, FS = FW * FH;
     constexpr int TW = TX + 2, TH = D == 3 ? TY + 2 : 1, TS = TW * TH;
     constexpr int NP = D * (D + 1) / 2;
-    constexpr int WA = D - 1;  // wall (march) axis component
+    constexpr int WA = D - 1;                    // wall (march) axis component
+    constexpr int NLD = (FS + NTH - 1) / NTH;    // field elements loaded per thread and plane
+    constexpr int NIP = D == 3 ? 9 : 3;          // in-plane neighbour offsets
     __shared__ R s_r[5][FS];
     __shared__ R s_p[5][FS];
     __shared__ R s_t[3][NP + 1][TS];
@@ -420,6 +439,7 @@ k_fused(KParams kp, const typename Ty<PREC>::S *__restrict__ fin, const typename
 
     const int tid = threadIdx.x;
     const int nx = kp.nx, ny = kp.ny, nw = kp.nw;
+    const unsigned N = (unsigned)kp.N, PS = (unsigned)kp.PS;
     const int ntx = (nx + TX - 1) / TX;
     const int x0 = (blockIdx.x % ntx) * TX;
     const int y0 = (D == 3) ? (blockIdx.x / ntx) * TY : 0;
@@ -434,29 +454,38 @@ k_fused(KParams kp, const typename Ty<PREC>::S *__restrict__ fin, const typename
     const R beta = (R)kp.beta, itg = (R)kp.inv_tau_g, Gam = (R)kp.Gamma;
     const R aeps = (R)kp.alpha_eps, atol = (R)kp.alpha_tol;
     const bool collide = !(kp.flags & 1u), alpha2 = (kp.flags & 2u) != 0;
+    const bool walls = kp.walls != 0;
 
-    auto fvalid = [&](int q) { return kp.walls ? (q >= 0 && q <= nw - 1) : true; };
-    auto tvalid = [&](int q) { return kp.walls ? (q >= 1 && q <= nw - 2) : true; };
-    auto plane = [&](int q) { return kp.walls ? q : wrapi(q, nw); };
+    // in-plane indices of the field elements this thread loads (fixed for the march)
+    unsigned ld_idx[NLD];
+#pragma unroll
+    for (int m = 0; m < NLD; ++m) {
+        int k = tid + m * NTH;
+        int lx = k % FW, ly = k / FW;
+        unsigned v = (unsigned)wrapl(x0 + lx - 2, nx);
+        if constexpr (D == 3) v += (unsigned)nx * (unsigned)wrapl(y0 + ly - 2, ny);
+        ld_idx[m] = v;
+    }
+    auto plane = [&](int q) { return walls ? q : wrap1(q, nw); };
 
     auto load_fields = [&](int q) {
-        if (!fvalid(q)) return;
-        int slot = (q + 10) % 5;
-        long long base = (long long)plane(q) * kp.PS;
-        for (int k = tid; k < FS; k += NTH) {
-            int lx = k % FW, ly = k / FW;
-            int gx = wrapi(x0 + lx - 2, nx);
-            long long n = base + gx;
-            if constexpr (D == 3) n += (long long)nx * wrapi(y0 + ly - 2, ny);
-            s_r[slot][k] = rho[n];
-            s_p[slot][k] = phi[n];
+        if (walls && (q < 0 || q > nw - 1)) return;
+        const int slot = (q + 10) % 5;
+        const unsigned base = (unsigned)plane(q) * PS;
+#pragma unroll
+        for (int m = 0; m < NLD; ++m) {
+            int k = tid + m * NTH;
+            if (NLD * NTH == FS || k < FS) {
+                s_r[slot][k] = rho[base + ld_idx[m]];
+                s_p[slot][k] = phi[base + ld_idx[m]];
+            }
         }
     };
 
     auto compute_T = [&](int q) {
-        if (!tvalid(q)) return;
-        int st = (q + 10) % 3;
-        int sm = (q + 9) % 5, s0 = (q + 10) % 5, sp = (q + 11) % 5;
+        if (walls && (q < 1 || q > nw - 2)) return;
+        const int st = (q + 10) % 3;
+        const int sm = (q + 9) % 5, s0 = (q + 10) % 5, sp = (q + 11) % 5;
         for (int k = tid; k < TS; k += NTH) {
             int hx = k % TW, hy = k / TW;
             int fc = (D == 3 ? (hy + 1) * FW : 0) + hx + 1;
@@ -464,22 +493,21 @@ k_fused(KParams kp, const typename Ty<PREC>::S *__restrict__ fin, const typename
             R r0 = s_r[s0][fc], p0 = s_p[s0][fc];
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
+                if (i == Q / 2) continue;
                 const int cw = cdir(D, i, WA);
                 const int off = cdir(D, i, 0) + (D == 3 ? cdir(D, i, 1) * FW : 0);
                 const int sl = cw < 0 ? sm : (cw > 0 ? sp : s0);
                 R rn = s_r[sl][fc + off], pn = s_p[sl][fc + off];
-                const R w3 = (R)(3.0 * wgt(D, i));
+                const R w3 = (R)(3.0 * wgt(D, i)), w6 = (R)(6.0 * wgt(D, i));
 #pragma unroll
                 for (int a = 0; a < D; ++a) {
                     if (cdir(D, i, a) != 0) {
-                        G[a] += w3 * (R)cdir(D, i, a) * rn;
-                        H[a] += w3 * (R)cdir(D, i, a) * pn;
+                        G[a] += (R)(cdir(D, i, a)) * w3 * rn;
+                        H[a] += (R)(cdir(D, i, a)) * w3 * pn;
                     }
                 }
-                if (i != Q / 2) {
-                    Lr += (R)(6.0 * wgt(D, i)) * (rn - r0);
-                    Lp += (R)(6.0 * wgt(D, i)) * (pn - p0);
-                }
+                Lr += w6 * (rn - r0);
+                Lp += w6 * (pn - p0);
             }
             R mur, mup, mP[NP];
             thermo<D, R>(th, r0, p0, G, H, Lr, Lp, mur, mup, mP);
@@ -500,6 +528,19 @@ k_fused(KParams kp, const typename Ty<PREC>::S *__restrict__ fin, const typename
     const bool active = x < nx && (D == 2 || y < ny);
     const int fcen = (D == 3 ? (ty + 2) * FW : 0) + tx + 2;
     const int tcen = (D == 3 ? (ty + 1) * TW : 0) + tx + 1;
+    // in-plane indices of x + (cx, cy) for every in-plane offset
+    unsigned nb[NIP];
+#pragma unroll
+    for (int k = 0; k < NIP; ++k) {
+        const int cx = (D == 3 ? k / 3 : k) - 1, cy = D == 3 ? k % 3 - 1 : 0;
+        unsigned v = (unsigned)wrap1(min(x, nx - 1) + cx, nx);
+        if constexpr (D == 3) v += (unsigned)nx * (unsigned)wrap1(min(y, ny - 1) + cy, ny);
+        nb[k] = v;
+    }
+    // in-plane index of population i's target
+    auto nbi = [&](int i) -> unsigned {
+        return D == 3 ? nb[(cdir(D, i, 0) + 1) * 3 + cdir(D, i, 1) + 1] : nb[cdir(D, i, 0) + 1];
+    };
     int my_cnt[3] = {0, 0, 0};
 
     for (int p = pb; p < pe; ++p) {
@@ -511,7 +552,7 @@ k_fused(KParams kp, const typename Ty<PREC>::S *__restrict__ fin, const typename
             const int sm = (p + 9) % 5, s0 = (p + 10) % 5, sp = (p + 11) % 5;
             const int tm = (p + 9) % 3, t0 = (p + 10) % 3, tp = (p + 11) % 3;
             const R r0 = s_r[s0][fcen], p0 = s_p[s0][fcen];
-            const bool first = kp.walls && (p == 1 || p == nw - 2);
+            const bool first = walls && (p == 1 || p == nw - 2);
             R F[3] = {0, 0, 0};
             if (first) {
                 // wall rule: normal derivatives dropped, in-layer differences
@@ -545,19 +586,20 @@ k_fused(KParams kp, const typename Ty<PREC>::S *__restrict__ fin, const typename
                     }
                 }
             }
-            if (kp.walls && kp.wetting == 0) {
+            if (walls && kp.wetting == 0) {
                 R rrel = (r0 - (R)kp.rho_g) * th.inv_drho, prel = p0 * th.inv_chi;
                 if (p == 2) F[WA] -= (R)(1.0 / 6.0) * rrel * ((R)kp.kw[0][0] + prel * (R)kp.kw[0][1]);
                 if (p == nw - 3) F[WA] += (R)(1.0 / 6.0) * rrel * ((R)kp.kw[1][0] + prel * (R)kp.kw[1][1]);
             }
-            const long long n = (long long)p * kp.PS + x + (D == 3 ? (long long)nx * y : 0);
+            const unsigned n = (unsigned)p * PS + nb[NIP / 2];
             R rp = (R)0, pp = (R)0;
             if constexpr (PREC == P16) { rp = rprev[n]; pp = pprev[n]; }
             R f[Q];
             R j[3] = {0, 0, 0};
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
-                f[i] = dec_f<PREC, D>(fin[(long long)i * kp.N + n], i, rp);
+                const S *fi = fin + (size_t)i * N;
+                f[i] = dec_f<PREC, D>(fi[n], i, rp);
 #pragma unroll
                 for (int a = 0; a < D; ++a)
                     if (cdir(D, i, a) != 0) j[a] += (R)cdir(D, i, a) * f[i];
@@ -572,29 +614,39 @@ k_fused(KParams kp, const typename Ty<PREC>::S *__restrict__ fin, const typename
                 v[a] = u[a] + (R)0.5 * du;
             }
             if (collide) {
-                R fe[Q], fd[Q];
-                feq<D, R>(r0, u, fe);
-                feq<D, R>(r0, ud, fd);
+                R fe[3][3], fd[3][3];
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    feq_factors(u[a], fe[a]);
+                    feq_factors(ud[a], fd[a]);
+                }
+                R dl[Q];
 #pragma unroll
                 for (int i = 0; i < Q; ++i) {
-                    R fpi = f[i] + fd[i] - fe[i];
-                    fe[i] = fd[i] - fpi;  // Delta
-                    f[i] = fpi;           // mirror state f'
+                    R e = r0 * fe[0][cdir(D, i, 0) + 1] * fe[1][cdir(D, i, 1) + 1];
+                    R d = r0 * fd[0][cdir(D, i, 0) + 1] * fd[1][cdir(D, i, 1) + 1];
+                    if constexpr (D == 3) {
+                        e *= fe[2][cdir(D, i, 2) + 1];
+                        d *= fd[2][cdir(D, i, 2) + 1];
+                    }
+                    R fpi = f[i] + d - e;
+                    dl[i] = d - fpi;  // Delta
+                    f[i] = fpi;       // mirror state f'
                 }
                 R al = (R)2;
                 bool is_x = false;
                 if (!alpha2) {
                     int kind;
-                    al = entropic_alpha<Q, R>(f, fe, aeps, atol, kp.alpha_maxit, kind, is_x);
+                    al = entropic_alpha<Q, R>(f, dl, aeps, atol, kp.alpha_maxit, kind, is_x);
                     my_cnt[kind == 1 ? 0 : (kind == 0 ? 1 : 2)]++;
                 }
                 const R ab = al * beta;
                 if (is_x) {
 #pragma unroll
-                    for (int i = 0; i < Q; ++i) f[i] += ab * (fe[i] * f[i]);
+                    for (int i = 0; i < Q; ++i) f[i] += ab * (dl[i] * f[i]);
                 } else {
 #pragma unroll
-                    for (int i = 0; i < Q; ++i) f[i] += ab * fe[i];
+                    for (int i = 0; i < Q; ++i) f[i] += ab * dl[i];
                 }
             }
             // stream f: push to x + c_i, halfway bounce-back at the walls
@@ -602,27 +654,30 @@ k_fused(KParams kp, const typename Ty<PREC>::S *__restrict__ fin, const typename
             for (int i = 0; i < Q; ++i) {
                 const int cw = cdir(D, i, WA);
                 const int pt = p + cw;
-                if (kp.walls && (pt < 1 || pt > nw - 2)) {
-                    fout[(long long)(Q - 1 - i) * kp.N + n] = enc_f<PREC, D>(f[i], Q - 1 - i, r0);
+                if (walls && (pt < 1 || pt > nw - 2)) {
+                    S *fo = fout + (size_t)(Q - 1 - i) * N;
+                    fo[n] = enc_f<PREC, D>(f[i], Q - 1 - i, r0);
                 } else {
                     const int offf = cdir(D, i, 0) + (D == 3 ? cdir(D, i, 1) * FW : 0);
                     const int slf = cw < 0 ? sm : (cw > 0 ? sp : s0);
-                    const long long nt = (long long)plane(pt) * kp.PS + wrapi(x + cdir(D, i, 0), nx) +
-                                         (D == 3 ? (long long)nx * wrapi(y + cdir(D, i, 1), ny) : 0);
-                    fout[(long long)i * kp.N + nt] = enc_f<PREC, D>(f[i], i, s_r[slf][fcen + offf]);
+                    const unsigned nt = (unsigned)plane(pt) * PS + nbi(i);
+                    S *fo = fout + (size_t)i * N;
+                    fo[nt] = enc_f<PREC, D>(f[i], i, s_r[slf][fcen + offf]);
                 }
             }
             // g: LBGK toward g^eq(phi, v) (Eqs. 33-35)
             R gg[Q];
 #pragma unroll
-            for (int i = 0; i < Q; ++i) gg[i] = dec_g<PREC, D>(gin[(long long)i * kp.N + n], i, pp);
+            for (int i = 0; i < Q; ++i) {
+                const S *gi = gin + (size_t)i * N;
+                gg[i] = dec_g<PREC, D>(gi[n], i, pp);
+            }
             if (collide) {
                 const R mup = s_t[t0][NP][tcen];
                 R vv = 0;
 #pragma unroll
                 for (int a = 0; a < D; ++a) vv += v[a] * v[a];
                 R sum = 0;
-                R ge[Q];
 #pragma unroll
                 for (int i = 0; i < Q; ++i) {
                     if (i == Q / 2) continue;
@@ -630,26 +685,26 @@ k_fused(KParams kp, const typename Ty<PREC>::S *__restrict__ fin, const typename
 #pragma unroll
                     for (int a = 0; a < D; ++a)
                         if (cdir(D, i, a) != 0) vc += (R)cdir(D, i, a) * v[a];
-                    ge[i] = (R)wgt(D, i) * ((R)3 * Gam * mup + (R)3 * p0 * vc + (R)4.5 * p0 * vc * vc -
-                                            (R)1.5 * p0 * vv);
-                    sum += ge[i];
+                    R ge = (R)wgt(D, i) * ((R)3 * Gam * mup + (R)3 * p0 * vc + (R)4.5 * p0 * vc * vc -
+                                           (R)1.5 * p0 * vv);
+                    sum += ge;
+                    gg[i] += (ge - gg[i]) * itg;
                 }
-                ge[Q / 2] = p0 - sum;
-#pragma unroll
-                for (int i = 0; i < Q; ++i) gg[i] += (ge[i] - gg[i]) * itg;
+                gg[Q / 2] += ((p0 - sum) - gg[Q / 2]) * itg;
             }
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 const int cw = cdir(D, i, WA);
                 const int pt = p + cw;
-                if (kp.walls && (pt < 1 || pt > nw - 2)) {
-                    gout[(long long)(Q - 1 - i) * kp.N + n] = enc_g<PREC, D>(gg[i], Q - 1 - i, p0);
+                if (walls && (pt < 1 || pt > nw - 2)) {
+                    S *go = gout + (size_t)(Q - 1 - i) * N;
+                    go[n] = enc_g<PREC, D>(gg[i], Q - 1 - i, p0);
                 } else {
                     const int offf = cdir(D, i, 0) + (D == 3 ? cdir(D, i, 1) * FW : 0);
                     const int slf = cw < 0 ? sm : (cw > 0 ? sp : s0);
-                    const long long nt = (long long)plane(pt) * kp.PS + wrapi(x + cdir(D, i, 0), nx) +
-                                         (D == 3 ? (long long)nx * wrapi(y + cdir(D, i, 1), ny) : 0);
-                    gout[(long long)i * kp.N + nt] = enc_g<PREC, D>(gg[i], i, s_p[slf][fcen + offf]);
+                    const unsigned nt = (unsigned)plane(pt) * PS + nbi(i);
+                    S *go = gout + (size_t)i * N;
+                    go[nt] = enc_g<PREC, D>(gg[i], i, s_p[slf][fcen + offf]);
                 }
             }
         }
