@@ -272,16 +272,25 @@ lbm3_status lbm3_init(lbm3 *h, const double *rho0, const double *phi0)
     return LBM3_OK;
 }
 
+// The launches of one step: moments, ghost layers (unless the fused kernel
+// fills them itself), then the fused update.
+static int launch_step(lbm3 *h, int which)
+{
+    const KParams &k = h->kp;
+    switch (which) {
+    case 0: return lbm3k::launch_moments(k, h->prec, h->b, h->pc, h->fc, h->stream);
+    case 1: return lbm3k::fused_fills_ghost(k) ? 0 : lbm3k::launch_ghost(k, h->prec, h->b, 1 - h->fc, h->stream);
+    default: return lbm3k::launch_fused(k, h->prec, h->b, h->pc, h->fc, h->stream);
+    }
+}
+
 lbm3_status lbm3_step(lbm3 *h, int64_t nsteps)
 {
     if (!h) return LBM3_EINVAL;
     if (!h->inited) return set_err(h, LBM3_ESTATE, "step before init");
     if (nsteps < 0) return set_err(h, LBM3_EINVAL, "negative step count");
-    const KParams &k = h->kp;
     for (int64_t t = 0; t < nsteps; ++t) {
-        if (lbm3k::launch_moments(k, h->prec, h->b, h->pc, h->fc, h->stream) ||
-            lbm3k::launch_ghost(k, h->prec, h->b, 1 - h->fc, h->stream) ||
-            lbm3k::launch_fused(k, h->prec, h->b, h->pc, h->fc, h->stream))
+        if (launch_step(h, 0) || launch_step(h, 1) || launch_step(h, 2))
             return set_err(h, LBM3_EDEVICE, "kernel launch failed");
         h->pc ^= 1;
         h->fc ^= 1;
@@ -290,58 +299,77 @@ lbm3_status lbm3_step(lbm3 *h, int64_t nsteps)
     return LBM3_OK;
 }
 
-lbm3_status lbm3_step_profiled(lbm3 *h, int64_t nsteps, double *kernel_ms)
+lbm3_status lbm3_step_profiled(lbm3 *h, int64_t nsteps, int32_t sample_every, double *kernel_ms)
 {
     if (!h) return LBM3_EINVAL;
     if (!h->inited) return set_err(h, LBM3_ESTATE, "step before init");
-    if (nsteps < 0) return set_err(h, LBM3_EINVAL, "negative step count");
-    const KParams &k = h->kp;
-    const int batch = 128;
-    std::vector<hipEvent_t> ev(4 * batch);
+    if (nsteps < 0 || sample_every < 1) return set_err(h, LBM3_EINVAL, "bad step count or sampling stride");
+    const int batch = 64;  // sampled steps between host synchronisations
+    hipEvent_t ev[4 * batch], first = nullptr, last = nullptr;
+    int made = 0;
     hipError_t e = hipSuccess;
-    for (auto &x : ev)
-        if ((e = hipEventCreate(&x)) != hipSuccess) return hip_err(h, e, "event create");
-    double acc[3] = {0, 0, 0}, span = 0;
-    hipEvent_t first = nullptr, last = nullptr;
-    hipEventCreate(&first);
-    hipEventCreate(&last);
-    hipEventRecord(first, h->stream);
     lbm3_status st = LBM3_OK;
-    for (int64_t t0 = 0; t0 < nsteps && st == LBM3_OK; t0 += batch) {
-        int nb = (int)std::min<int64_t>(batch, nsteps - t0);
-        for (int s = 0; s < nb; ++s) {
-            hipEventRecord(ev[4 * s], h->stream);
-            int r1 = lbm3k::launch_moments(k, h->prec, h->b, h->pc, h->fc, h->stream);
-            hipEventRecord(ev[4 * s + 1], h->stream);
-            int r2 = lbm3k::launch_ghost(k, h->prec, h->b, 1 - h->fc, h->stream);
-            hipEventRecord(ev[4 * s + 2], h->stream);
-            int r3 = lbm3k::launch_fused(k, h->prec, h->b, h->pc, h->fc, h->stream);
-            hipEventRecord(ev[4 * s + 3], h->stream);
-            if (r1 || r2 || r3) { st = set_err(h, LBM3_EDEVICE, "kernel launch failed"); break; }
-            h->pc ^= 1;
-            h->fc ^= 1;
-            h->step++;
-        }
-        if ((e = hipEventSynchronize(ev[4 * nb - 1])) != hipSuccess) { st = hip_err(h, e, "profiled step"); break; }
-        for (int s = 0; s < nb; ++s)
+    double acc[3] = {0, 0, 0}, span = 0;
+    int64_t sampled = 0;
+    for (; made < 4 * batch; ++made)
+        if ((e = hipEventCreate(&ev[made])) != hipSuccess) break;
+    if (e == hipSuccess) e = hipEventCreate(&first);
+    if (e == hipSuccess) e = hipEventCreate(&last);
+    if (e == hipSuccess) e = hipEventRecord(first, h->stream);
+    if (e != hipSuccess) st = hip_err(h, e, "event setup");
+    int pending = 0;  // sampled steps whose events are not yet read
+    auto drain = [&]() -> bool {
+        if (!pending) return true;
+        if ((e = hipEventSynchronize(ev[4 * pending - 1])) != hipSuccess) return false;
+        for (int s = 0; s < pending; ++s)
             for (int j = 0; j < 3; ++j) {
+                // a step without the ghost-layer launch leaves E[2] unrecorded
+                const bool skip = lbm3k::fused_fills_ghost(h->kp);
+                if (j == 1 && skip) continue;
+                const int from = (j == 2 && skip) ? 1 : j;
                 float ms = 0;
-                hipEventElapsedTime(&ms, ev[4 * s + j], ev[4 * s + j + 1]);
+                if ((e = hipEventElapsedTime(&ms, ev[4 * s + from], ev[4 * s + j + 1])) != hipSuccess) return false;
                 acc[j] += ms;
             }
+        sampled += pending;
+        pending = 0;
+        return true;
+    };
+    for (int64_t t = 0; t < nsteps && st == LBM3_OK; ++t) {
+        const bool timed = t % sample_every == 0;
+        hipEvent_t *E = ev + 4 * pending;
+        int r = 0;
+        if (timed && (e = hipEventRecord(E[0], h->stream)) != hipSuccess) { st = hip_err(h, e, "event record"); break; }
+        for (int j = 0; j < 3 && !r; ++j) {
+            if (j == 1 && lbm3k::fused_fills_ghost(h->kp)) continue;
+            r = launch_step(h, j);
+            if (!r && timed && (e = hipEventRecord(E[j + 1], h->stream)) != hipSuccess) {
+                st = hip_err(h, e, "event record");
+                break;
+            }
+        }
+        if (st != LBM3_OK) break;
+        if (r) { st = set_err(h, LBM3_EDEVICE, "kernel launch failed"); break; }
+        h->pc ^= 1;
+        h->fc ^= 1;
+        h->step++;
+        if (timed && ++pending == batch && !drain()) st = hip_err(h, e, "profiled step");
     }
-    hipEventRecord(last, h->stream);
-    if (hipEventSynchronize(last) == hipSuccess) {
+    if (st == LBM3_OK && !drain()) st = hip_err(h, e, "profiled step");
+    if (st == LBM3_OK) {
         float ms = 0;
-        hipEventElapsedTime(&ms, first, last);
+        if ((e = hipEventRecord(last, h->stream)) != hipSuccess || (e = hipEventSynchronize(last)) != hipSuccess ||
+            (e = hipEventElapsedTime(&ms, first, last)) != hipSuccess)
+            st = hip_err(h, e, "profiled span");
         span = ms;
     }
-    for (auto &x : ev) hipEventDestroy(x);
-    hipEventDestroy(first);
-    hipEventDestroy(last);
+    for (int i = 0; i < made; ++i) (void)hipEventDestroy(ev[i]);
+    if (first) (void)hipEventDestroy(first);
+    if (last) (void)hipEventDestroy(last);
     if (kernel_ms) {
-        for (int j = 0; j < 3; ++j) kernel_ms[j] = acc[j];
+        for (int j = 0; j < 3; ++j) kernel_ms[j] = sampled ? acc[j] / (double)sampled : 0.0;
         kernel_ms[3] = span;
+        kernel_ms[4] = (double)sampled;
     }
     return st;
 }

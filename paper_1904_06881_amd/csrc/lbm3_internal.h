@@ -43,6 +43,8 @@ struct Buffers {
 int launch_moments(const KParams &kp, int prec, const Buffers &b, int pc, int fc, void *stream);
 int launch_ghost(const KParams &kp, int prec, const Buffers &b, int fdst, void *stream);
 int launch_fused(const KParams &kp, int prec, const Buffers &b, int pc, int fc, void *stream);
+// true when the fused kernel fills the wall ghost layers itself (2D)
+bool fused_fills_ghost(const KParams &kp);
 int launch_init(const KParams &kp, int prec, const Buffers &b, void *stream);
 int launch_init_field(const KParams &kp, int prec, const Buffers &b, int which, void *stream);
 int launch_observe(const KParams &kp, int prec, const Buffers &b, int pc, int fc, void *stream);

@@ -4,14 +4,16 @@
 // Data layout in HBM: populations SoA [Q][N] (x fastest), two buffers per
 // set (push streaming writes the other one); fields rho, phi [N] in the
 // compute type, two buffers (the FP16 storage decodes with the previous
-// step's fields).  A step is three launches:
+// step's fields).  A step is two launches in 2D and three in 3D:
 //   k_moments  rho, phi of every fluid node from its populations;
-//   k_ghost    wall ghost layers of rho, phi;
+//   k_ghost    (3D) wall ghost layers of rho, phi;
 //   k_fused    per block an in-plane tile (x in 2D, x-y in 3D) marching along
-//              the wall axis: a 5-plane LDS ring of rho, phi with halo 2, a
-//              3-plane LDS ring of -P and mu_phi with halo 1, then force,
-//              entropic collision of f, LBGK of g and push streaming with
-//              halfway bounce-back for one plane at a time.
+//              the wall axis: a 5-plane LDS ring of rho, phi with halo 3 (in
+//              2D the wall ghost layers are filled in the block), a 3-plane
+//              LDS ring of -P and mu_phi with halo 1, then force, entropic
+//              collision of f, LBGK of g and push streaming with halfway
+//              bounce-back for one plane at a time.
+// k_ghost also fills the ghost layers for initialisation and export.
 #include <hip/hip_runtime.h>
 
 #include "lbm3_internal.h"
@@ -192,16 +194,18 @@ __device__ __forceinline__ void feq(R rho, const R *u, R *fe)
 }
 
 // Entropic alpha: non-trivial root of H(f' + alpha Delta) = H(f'), Eqs. 30-32,
-// as G(alpha) = sum f'[(1 + alpha x) log1p(alpha x) - alpha x (1 + log1p(x))]
-// with x = Delta/f': the terms linear in ln(f^eq/w) and alpha sum Delta vanish
-// because Delta carries no mass or momentum, and leaving them out keeps the
-// root free of their rounding.  kind: 0 small deviation (max|x| < eps, root
-// from the expansion of G about alpha = 2: 2 + (S3 - 2 S4)/(3 S2 - 4 S3),
-// S_k = sum f' x^k), 1 Newton root, 2 fallback (non-positive f' or no
-// convergence).  Iterates are kept in (1, alpha_max), alpha_max = min_{x<0}
-// -1/x the positivity limit; iteration stops when |step| < tol or when a step
-// below 10 tol fails to halve the previous one (resolved to rounding).  On return dx holds x (is_x = true) or, after a
-// non-positive f', still Delta.
+// as G(alpha) = sum f'[(1 + alpha x) log1p(alpha x) - alpha x] - alpha K,
+// x = Delta/f', K = sum f' x log1p(x): the terms linear in ln(f^eq/w) and
+// alpha sum Delta vanish because Delta carries no mass or momentum, and
+// leaving them out keeps the root free of their rounding.  The expansion of
+// G about alpha = 2 gives alpha_s = 2 + (S3 - 2 S4)/(3 S2 - 4 S3), S_k =
+// sum f' x^k.  kind: 0 small deviation (max|x| < eps: alpha_s is the root to
+// O(x^3)), 1 Newton root, 2 fallback (non-positive f' or no convergence).
+// Newton starts from alpha_s (one step fewer than from alpha = 2 on typical
+// interface states); its iterates are kept in (1, alpha_max), alpha_max =
+// min_{x<0} -1/x the positivity limit.  It stops when |step| < tol or when a step below 10 tol
+// fails to halve the previous one (resolved to rounding).  On return dx holds
+// x (is_x = true) or, after a non-positive f', still Delta.
 template <int Q, typename R>
 __device__ __forceinline__ R entropic_alpha(const R *fp, R *dx, R eps, R tol, int maxit, int &kind,
                                             bool &is_x)
@@ -212,45 +216,45 @@ __device__ __forceinline__ R entropic_alpha(const R *fp, R *dx, R eps, R tol, in
     if (!pos) { kind = 2; is_x = false; return (R)2; }
     is_x = true;
     R xmax = 0, amax = (R)INFINITY;
+    R S2 = 0, S3 = 0, S4 = 0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        dx[i] = dx[i] / fp[i];
-        xmax = fmax(xmax, fabs(dx[i]));
-        if (dx[i] < (R)0) amax = fmin(amax, (R)-1 / dx[i]);
+        const R x = dx[i] / fp[i];
+        dx[i] = x;
+        xmax = fmax(xmax, fabs(x));
+        if (x < (R)0) amax = fmin(amax, (R)-1 / x);
+        const R x2 = x * x;
+        S2 += fp[i] * x2;
+        S3 += fp[i] * x2 * x;
+        S4 += fp[i] * x2 * x2;
     }
-    if (xmax < eps) {
-        kind = 0;
-        R S2 = 0, S3 = 0, S4 = 0;
+    const R den = (R)3 * S2 - (R)4 * S3;
+    const R as = den > (R)0 ? (R)2 + (S3 - (R)2 * S4) / den : (R)2;
+    if (xmax < eps) { kind = 0; return as; }
+    R K = 0;
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            R x2 = dx[i] * dx[i];
-            S2 += fp[i] * x2;
-            S3 += fp[i] * x2 * dx[i];
-            S4 += fp[i] * x2 * x2;
-        }
-        R den = (R)3 * S2 - (R)4 * S3;
-        return den > (R)0 ? (R)2 + (S3 - (R)2 * S4) / den : (R)2;
-    }
-    R l1[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) l1[i] = log1p(dx[i]);
-    R al = ((R)2 < amax) ? (R)2 : (R)0.5 * ((R)1 + amax);
+    for (int i = 0; i < Q; ++i) K += fp[i] * dx[i] * log1p(dx[i]);
+    R al;
+    if (den > (R)0 && as > (R)1 && as < amax) al = as;
+    else al = ((R)2 < amax) ? (R)2 : (R)0.5 * ((R)1 + amax);
     const R stag = (R)10 * tol;
     R prev = (R)INFINITY;
     for (int it = 0; it < maxit; ++it) {
-        R G = 0, dG = 0;
+        R G = 0, G1 = 0;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            R ax = al * dx[i];
-            R la = log1p(ax);
-            G += fp[i] * (((R)1 + ax) * la - ax * ((R)1 + l1[i]));
-            dG += fp[i] * dx[i] * (la - l1[i]);
+            const R ax = al * dx[i];
+            const R la = log1p(ax);
+            G += fp[i] * (((R)1 + ax) * la - ax);
+            G1 += fp[i] * dx[i] * la;
         }
-        if (!(dG > (R)0)) break;
-        R an = al - G / dG;
+        G -= al * K;
+        G1 -= K;
+        if (!(G1 > (R)0)) break;
+        R an = al - G / G1;
         if (an >= amax) an = (R)0.5 * (al + amax);
         if (an <= (R)1) an = (R)0.5 * (al + (R)1);
-        R st = fabs(an - al);
+        const R st = fabs(an - al);
         if (st < tol || (st < stag && st > (R)0.5 * prev)) { kind = 1; return an; }
         prev = st;
         al = an;
@@ -300,20 +304,37 @@ __device__ __forceinline__ int classify(R ngr, R ngp, R dot, R r, R ph, R rho_l,
     return k;
 }
 
-template <typename R>
-__device__ __forceinline__ R interp2(const R *q, long long base, int nx, int i, R l)
+// linear interpolation along the wall at offset l, Eq. 47; get(dx, dy, r, p)
+// returns the first fluid layer at in-plane offset (dx, dy) from the node
+template <typename R, typename Get>
+__device__ __forceinline__ void interp2(Get get, R l, R &r, R &ph)
 {
     R l0 = floor(l), l1 = l0 + (R)1;
-    R q0 = q[base + wrapi(i + (int)l0, nx)];
-    if (l == l0) return q0;  // exact lattice copy at integer shifts
-    R q1 = q[base + wrapi(i + (int)l1, nx)];
-    return (q1 - q0) * l + (l1 * q0 - l0 * q1);
+    R r0, p0;
+    get((int)l0, 0, r0, p0);
+    if (l == l0) { r = r0; ph = p0; return; }  // exact lattice copy at integer shifts
+    R r1, p1;
+    get((int)l1, 0, r1, p1);
+    r = (r1 - r0) * l + (l1 * r0 - l0 * r1);
+    ph = (p1 - p0) * l + (l1 * p0 - l0 * p1);
 }
 
 // plane through the three corners of the unit cell nearest to (lx, ly),
 // Eqs. 48-49
 template <typename R>
-__device__ __forceinline__ R interp3(const R *q, long long base, int nx, int ny, int i, int j, R lx, R ly)
+__device__ __forceinline__ R plane3(const R *X, const R *Y, const R *Cv, R lx, R ly)
+{
+    R x1 = X[0], x2 = X[1], x3 = X[2], y1 = Y[0], y2 = Y[1], y3 = Y[2];
+    R c1 = Cv[0], c2 = Cv[1], c3 = Cv[2];
+    R A = y2 * c1 - y3 * c1 - y1 * c2 + y3 * c2 + y1 * c3 - y2 * c3;
+    R B = -x2 * c1 + x3 * c1 + x1 * c2 - x3 * c2 - x1 * c3 + x2 * c3;
+    R Cc = -x3 * y2 * c1 + x2 * y3 * c1 + x3 * y1 * c2 - x1 * y3 * c2 - x2 * y1 * c3 + x1 * y2 * c3;
+    R Dd = -x2 * y1 + x3 * y1 + x1 * y2 - x3 * y2 - x1 * y3 + x2 * y3;
+    return (A * lx + B * ly + Cc) / Dd;
+}
+
+template <typename R, typename Get>
+__device__ __forceinline__ void interp3(Get get, R lx, R ly, R &r, R &ph)
 {
     R x0 = floor(lx), y0 = floor(ly);
     R fx = lx - x0, fy = ly - y0;
@@ -325,23 +346,66 @@ __device__ __forceinline__ R interp3(const R *q, long long base, int nx, int ny,
         R d = (fx - cx[k]) * (fx - cx[k]) + (fy - cy[k]) * (fy - cy[k]);
         if (d > dmax) { dmax = d; drop = k; }
     }
-    R X[3], Y[3], Cv[3];
+    R X[3], Y[3], Cr[3], Cp[3];
     int m = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         if (k == drop) continue;
         X[m] = x0 + cx[k];
         Y[m] = y0 + cy[k];
-        Cv[m] = q[base + wrapi(i + (int)X[m], nx) + (long long)nx * wrapi(j + (int)Y[m], ny)];
+        get((int)X[m], (int)Y[m], Cr[m], Cp[m]);
         ++m;
     }
-    R x1 = X[0], x2 = X[1], x3 = X[2], y1 = Y[0], y2 = Y[1], y3 = Y[2];
-    R c1 = Cv[0], c2 = Cv[1], c3 = Cv[2];
-    R A = y2 * c1 - y3 * c1 - y1 * c2 + y3 * c2 + y1 * c3 - y2 * c3;
-    R B = -x2 * c1 + x3 * c1 + x1 * c2 - x3 * c2 - x1 * c3 + x2 * c3;
-    R Cc = -x3 * y2 * c1 + x2 * y3 * c1 + x3 * y1 * c2 - x1 * y3 * c2 - x2 * y1 * c3 + x1 * y2 * c3;
-    R Dd = -x2 * y1 + x3 * y1 + x1 * y2 - x3 * y2 - x1 * y3 + x2 * y3;
-    return (A * lx + B * ly + Cc) / Dd;
+    r = plane3(X, Y, Cr, lx, ly);
+    ph = plane3(X, Y, Cp, lx, ly);
+}
+
+// Ghost-layer values of one wall node (Sec. IV): copy of the first fluid
+// layer for the force method, else the geometric wetting condition with the
+// contact angle of the interface found by the detection rules.
+template <int D, typename R, typename Get>
+__device__ __forceinline__ void ghost_value(const KParams &kp, int wall, Get get, R &out_r, R &out_p)
+{
+    R r0, p0;
+    get(0, 0, r0, p0);
+    out_r = r0;
+    out_p = p0;
+    if (kp.wetting == 0) return;
+    R drho = (R)kp.drho, chi = (R)kp.chi;
+    R gr[2] = {0, 0}, gp[2] = {0, 0};
+    R ra, pa, rb, pb;
+    get(1, 0, ra, pa);
+    get(-1, 0, rb, pb);
+    gr[0] = (R)0.5 * (ra - rb);
+    gp[0] = (R)0.5 * (pa - pb);
+    if constexpr (D == 3) {
+        get(0, 1, ra, pa);
+        get(0, -1, rb, pb);
+        gr[1] = (R)0.5 * (ra - rb);
+        gp[1] = (R)0.5 * (pa - pb);
+    }
+    R ngr = sqrt(gr[0] * gr[0] + gr[1] * gr[1]);
+    R ngp = sqrt(gp[0] * gp[0] + gp[1] * gp[1]);
+    if (ngr < (R)1e-12 * drho && ngp < (R)1e-12 * drho) return;
+    R dot = gr[0] * gp[0] + gr[1] * gp[1];
+    int cls = classify(ngr, ngp, dot, r0, p0, (R)kp.rho_l, drho, chi);
+    R ct = (R)kp.cot[wall][cls];
+    const R *gc = cls == 2 ? gp : gr;
+    R ngc = cls == 2 ? ngp : ngr;
+    if (kp.wetting == 2) {
+        // geometric extrapolation (Eqs. 45-46), per field along m
+        if (ngc != (R)0) {
+            R m0 = gc[0] / ngc, m1 = gc[1] / ngc;
+            out_r = r0 + ct * (gr[0] * m0 + gr[1] * m1);
+            out_p = p0 + ct * (gp[0] * m0 + gp[1] * m1);
+        }
+    } else if constexpr (D == 2) {
+        // shift by cot(theta) toward the measuring phase (+grad c)
+        R sg = gc[0] > (R)0 ? (R)1 : (gc[0] < (R)0 ? (R)-1 : (R)0);
+        interp2(get, sg * ct, out_r, out_p);
+    } else {
+        if (ngc != (R)0) interp3(get, ct * gc[0] / ngc, ct * gc[1] / ngc, out_r, out_p);
+    }
 }
 
 template <int D, typename R>
@@ -356,48 +420,14 @@ k_ghost(KParams kp, R *__restrict__ rho, R *__restrict__ phi)
     int k = t % np;
     int i = k % nx, j = (D == 2) ? 0 : k / nx;
     int kg = wall == 0 ? 0 : kp.nw - 1, kf = wall == 0 ? 1 : kp.nw - 2;
-    long long bf = (long long)kf * kp.PS, bg = (long long)kg * kp.PS;
-    long long nf = bf + i + (long long)nx * j, ng = bg + i + (long long)nx * j;
-    R r0 = rho[nf], p0 = phi[nf];
-    if (kp.wetting == 0) { rho[ng] = r0; phi[ng] = p0; return; }
-    R drho = (R)kp.drho, chi = (R)kp.chi;
-    R gr[2] = {0, 0}, gp[2] = {0, 0};
-    gr[0] = (R)0.5 * (rho[bf + wrapi(i + 1, nx) + (long long)nx * j] - rho[bf + wrapi(i - 1, nx) + (long long)nx * j]);
-    gp[0] = (R)0.5 * (phi[bf + wrapi(i + 1, nx) + (long long)nx * j] - phi[bf + wrapi(i - 1, nx) + (long long)nx * j]);
-    if constexpr (D == 3) {
-        gr[1] = (R)0.5 * (rho[bf + i + (long long)nx * wrapi(j + 1, ny)] - rho[bf + i + (long long)nx * wrapi(j - 1, ny)]);
-        gp[1] = (R)0.5 * (phi[bf + i + (long long)nx * wrapi(j + 1, ny)] - phi[bf + i + (long long)nx * wrapi(j - 1, ny)]);
-    }
-    R ngr = sqrt(gr[0] * gr[0] + gr[1] * gr[1]);
-    R ngp = sqrt(gp[0] * gp[0] + gp[1] * gp[1]);
-    R out_r = r0, out_p = p0;
-    if (!(ngr < (R)1e-12 * drho && ngp < (R)1e-12 * drho)) {
-        R dot = gr[0] * gp[0] + gr[1] * gp[1];
-        int cls = classify(ngr, ngp, dot, r0, p0, (R)kp.rho_l, drho, chi);
-        R ct = (R)kp.cot[wall][cls];
-        const R *gc = cls == 2 ? gp : gr;
-        R ngc = cls == 2 ? ngp : ngr;
-        if (kp.wetting == 2) {
-            // geometric extrapolation (Eqs. 45-46), per field along m
-            if (ngc != (R)0) {
-                R m0 = gc[0] / ngc, m1 = gc[1] / ngc;
-                out_r = r0 + ct * (gr[0] * m0 + gr[1] * m1);
-                out_p = p0 + ct * (gp[0] * m0 + gp[1] * m1);
-            }
-        } else if constexpr (D == 2) {
-            // shift by cot(theta) toward the measuring phase (+grad c)
-            R sg = gc[0] > (R)0 ? (R)1 : (gc[0] < (R)0 ? (R)-1 : (R)0);
-            R l = sg * ct;
-            out_r = interp2(rho, bf, nx, i, l);
-            out_p = interp2(phi, bf, nx, i, l);
-        } else {
-            if (ngc != (R)0) {
-                R lx = ct * gc[0] / ngc, ly = ct * gc[1] / ngc;
-                out_r = interp3(rho, bf, nx, ny, i, j, lx, ly);
-                out_p = interp3(phi, bf, nx, ny, i, j, lx, ly);
-            }
-        }
-    }
+    long long bf = (long long)kf * kp.PS, ng = (long long)kg * kp.PS + i + (long long)nx * j;
+    auto get = [&](int dx, int dy, R &r, R &ph) {
+        long long n = bf + wrapi(i + dx, nx) + (D == 3 ? (long long)nx * wrapi(j + dy, ny) : 0);
+        r = rho[n];
+        ph = phi[n];
+    };
+    R out_r, out_p;
+    ghost_value<D, R>(kp, wall, get, out_r, out_p);
     rho[ng] = out_r;
     phi[ng] = out_p;
 }
@@ -413,20 +443,26 @@ __device__ __forceinline__ int wrapl(int v, int n)
     return v;
 }
 
-template <int D, int PREC, int TX, int TY>
-__global__ void __launch_bounds__(TX * TY)
-__attribute__((amdgpu_waves_per_eu(D == 3 ? (PREC == P64 ? 1 : 2) : (PREC == P64 ? 2 : 4))))
+// One block updates a TX x TY tile (TY = 1 in 2D) of every plane in its
+// chunk with NTH >= TX TY threads; NTH = (TX + 2)(TY + 2) in 2D makes the
+// -P stage one pass per plane.  In 2D the wall ghost layers of rho, phi are
+// filled by the blocks themselves from the first fluid layer (and written
+// back for their own nodes), so a step is the moments kernel and this one;
+// in 3D the ghost-layer kernel runs in between.
+template <int D, int PREC, int TX, int TY, int NTH>
+__global__ void __launch_bounds__(NTH)
+__attribute__((amdgpu_waves_per_eu(D == 3 ? (PREC == P64 ? 1 : 2) : (PREC == P64 ? 2 : (NTH <= 64 ? 3 : 4)))))
 k_fused(KParams kp, const typename Ty<PREC>::S *__restrict__ fin, const typename Ty<PREC>::S *__restrict__ gin,
         typename Ty<PREC>::S *__restrict__ fout, typename Ty<PREC>::S *__restrict__ gout,
-        const typename Ty<PREC>::R *__restrict__ rho, const typename Ty<PREC>::R *__restrict__ phi,
+        typename Ty<PREC>::R *__restrict__ rho, typename Ty<PREC>::R *__restrict__ phi,
         const typename Ty<PREC>::R *__restrict__ rprev, const typename Ty<PREC>::R *__restrict__ pprev,
         unsigned long long *__restrict__ cnt, int chunk)
 {
     using R = typename Ty<PREC>::R;
     using S = typename Ty<PREC>::S;
     constexpr int Q = D == 2 ? 9 : 27;
-    constexpr int NTH = TX * TY;
-    constexpr int FW = TX + 4, FH = D == 3 ? TY + 4 : 1, FS = FW * FH;
+    constexpr int HF = 3;                        // halo of the rho, phi tile
+    constexpr int FW = TX + 2 * HF, FH = D == 3 ? TY + 2 * HF : 1, FS = FW * FH;
     constexpr int TW = TX + 2, TH = D == 3 ? TY + 2 : 1, TS = TW * TH;
     constexpr int NP = D * (D + 1) / 2;
     constexpr int WA = D - 1;                    // wall (march) axis component
@@ -456,20 +492,31 @@ k_fused(KParams kp, const typename Ty<PREC>::S *__restrict__ fin, const typename
     const bool collide = !(kp.flags & 1u), alpha2 = (kp.flags & 2u) != 0;
     const bool walls = kp.walls != 0;
 
-    // in-plane indices of the field elements this thread loads (fixed for the march)
+    // in-plane indices of the field elements this thread loads (fixed for
+    // the march) and whether the element is one of the block's own nodes
     unsigned ld_idx[NLD];
+    unsigned own = 0;
 #pragma unroll
     for (int m = 0; m < NLD; ++m) {
         int k = tid + m * NTH;
         int lx = k % FW, ly = k / FW;
-        unsigned v = (unsigned)wrapl(x0 + lx - 2, nx);
-        if constexpr (D == 3) v += (unsigned)nx * (unsigned)wrapl(y0 + ly - 2, ny);
+        unsigned v = (unsigned)wrapl(x0 + lx - HF, nx);
+        if constexpr (D == 3) v += (unsigned)nx * (unsigned)wrapl(y0 + ly - HF, ny);
         ld_idx[m] = v;
+        bool o = k < FS && lx >= HF && lx < TX + HF && x0 + lx - HF < nx;
+        if constexpr (D == 3) o = o && ly >= HF && ly < TY + HF && y0 + ly - HF < ny;
+        own |= (o ? 1u : 0u) << m;
     }
-    auto plane = [&](int q) { return walls ? q : wrap1(q, nw); };
+    auto plane = [&](int q) { return walls ? q : wrapl(q, nw); };
 
+    // 2D: the block fills the wall ghost layers itself (one launch fewer per
+    // step); 3D: they come filled from the ghost-layer kernel
+    constexpr bool GK = D == 2;
+
+    // plane q of rho, phi into the LDS ring (ghost layers: ghost_plane)
     auto load_fields = [&](int q) {
         if (walls && (q < 0 || q > nw - 1)) return;
+        if (GK && walls && (q == 0 || q == nw - 1)) return;
         const int slot = (q + 10) % 5;
         const unsigned base = (unsigned)plane(q) * PS;
 #pragma unroll
@@ -482,13 +529,51 @@ k_fused(KParams kp, const typename Ty<PREC>::S *__restrict__ fin, const typename
         }
     };
 
+    // Wall ghost layer q (0 or nw - 1) over the tile and a halo of 2 (Sec. IV)
+    // from the first fluid layer, which is in the ring; the wetting condition
+    // reads it within the tile's halo of HF = 3 from LDS and further out along
+    // the wall (contact angles far from 90 degrees) from rho, phi.
+    auto ghost_plane = [&](int q) {
+        if constexpr (!GK) return;
+        const int wall = q == 0 ? 0 : 1;
+        const int kf = wall == 0 ? 1 : nw - 2;
+        const int sg = (q + 10) % 5, sf = (kf + 10) % 5;
+        const unsigned bf = (unsigned)kf * PS, bg = (unsigned)q * PS;
+        for (int m = 0; m < NLD; ++m) {
+            const int k = tid + m * NTH;
+            if (NLD * NTH != FS && k >= FS) continue;
+            const int lx = k % FW, ly = k / FW;
+            if (lx < HF - 2 || lx >= FW - HF + 2 || (D == 3 && (ly < HF - 2 || ly >= FH - HF + 2))) continue;
+            auto get = [&](int dx, int dy, R &r, R &ph) {
+                const int jx = lx + dx, jy = ly + dy;
+                if (jx >= 0 && jx < FW && jy >= 0 && jy < FH) {
+                    r = s_r[sf][jy * FW + jx];
+                    ph = s_p[sf][jy * FW + jx];
+                } else {
+                    unsigned n = bf + (unsigned)wrapl(x0 + jx - HF, nx);
+                    if constexpr (D == 3) n += (unsigned)nx * (unsigned)wrapl(y0 + jy - HF, ny);
+                    r = rho[n];
+                    ph = phi[n];
+                }
+            };
+            R gr_, gp_;
+            ghost_value<D, R>(kp, wall, get, gr_, gp_);
+            s_r[sg][k] = gr_;
+            s_p[sg][k] = gp_;
+            if (own & (1u << m)) {
+                rho[bg + ld_idx[m]] = gr_;
+                phi[bg + ld_idx[m]] = gp_;
+            }
+        }
+    };
+
     auto compute_T = [&](int q) {
         if (walls && (q < 1 || q > nw - 2)) return;
         const int st = (q + 10) % 3;
         const int sm = (q + 9) % 5, s0 = (q + 10) % 5, sp = (q + 11) % 5;
         for (int k = tid; k < TS; k += NTH) {
             int hx = k % TW, hy = k / TW;
-            int fc = (D == 3 ? (hy + 1) * FW : 0) + hx + 1;
+            int fc = (D == 3 ? (hy + HF - 1) * FW : 0) + hx + HF - 1;
             R G[3] = {0, 0, 0}, H[3] = {0, 0, 0}, Lr = 0, Lp = 0;
             R r0 = s_r[s0][fc], p0 = s_p[s0][fc];
 #pragma unroll
@@ -520,13 +605,18 @@ k_fused(KParams kp, const typename Ty<PREC>::S *__restrict__ fin, const typename
     // prologue: fields pb-2 .. pb+1, -P planes pb-1 .. pb
     for (int q = pb - 2; q <= pb + 1; ++q) load_fields(q);
     __syncthreads();
+    if (GK && walls && (pb - 2 <= 0 || pb + 1 >= nw - 1)) {
+        for (int q = pb - 2; q <= pb + 1; ++q)
+            if (q == 0 || q == nw - 1) ghost_plane(q);
+        __syncthreads();
+    }
     compute_T(pb - 1);
     compute_T(pb);
 
     const int tx = tid % TX, ty = tid / TX;
     const int x = x0 + tx, y = y0 + ty;
-    const bool active = x < nx && (D == 2 || y < ny);
-    const int fcen = (D == 3 ? (ty + 2) * FW : 0) + tx + 2;
+    const bool active = tid < TX * TY && x < nx && (D == 2 || y < ny);
+    const int fcen = (D == 3 ? (ty + HF) * FW : 0) + tx + HF;
     const int tcen = (D == 3 ? (ty + 1) * TW : 0) + tx + 1;
     // in-plane indices of x + (cx, cy) for every in-plane offset
     unsigned nb[NIP];
@@ -543,7 +633,24 @@ k_fused(KParams kp, const typename Ty<PREC>::S *__restrict__ fin, const typename
     };
     int my_cnt[3] = {0, 0, 0};
 
+    // PF: issue this plane's population loads before the field stage, so
+    // their latency overlaps the stencil work (registers permitting)
+    constexpr bool PF = D == 2;
+    constexpr int QF = PF ? Q : 1;
     for (int p = pb; p < pe; ++p) {
+        // the far ghost layer from plane p + 1, before this plane's loads
+        if (GK && walls && p + 2 == nw - 1) ghost_plane(p + 2);
+        const unsigned n = (unsigned)p * PS + nb[NIP / 2];
+        S fr[QF], gr[QF];
+        if constexpr (PF) {
+            if (active) {
+#pragma unroll
+                for (int i = 0; i < Q; ++i) {
+                    fr[i] = fin[(size_t)i * N + n];
+                    gr[i] = gin[(size_t)i * N + n];
+                }
+            }
+        }
         load_fields(p + 2);
         __syncthreads();
         compute_T(p + 1);
@@ -591,7 +698,6 @@ k_fused(KParams kp, const typename Ty<PREC>::S *__restrict__ fin, const typename
                 if (p == 2) F[WA] -= (R)(1.0 / 6.0) * rrel * ((R)kp.kw[0][0] + prel * (R)kp.kw[0][1]);
                 if (p == nw - 3) F[WA] += (R)(1.0 / 6.0) * rrel * ((R)kp.kw[1][0] + prel * (R)kp.kw[1][1]);
             }
-            const unsigned n = (unsigned)p * PS + nb[NIP / 2];
             R rp = (R)0, pp = (R)0;
             if constexpr (PREC == P16) { rp = rprev[n]; pp = pprev[n]; }
             R f[Q];
@@ -599,7 +705,7 @@ k_fused(KParams kp, const typename Ty<PREC>::S *__restrict__ fin, const typename
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 const S *fi = fin + (size_t)i * N;
-                f[i] = dec_f<PREC, D>(fi[n], i, rp);
+                f[i] = dec_f<PREC, D>(PF ? fr[PF ? i : 0] : fi[n], i, rp);
 #pragma unroll
                 for (int a = 0; a < D; ++a)
                     if (cdir(D, i, a) != 0) j[a] += (R)cdir(D, i, a) * f[i];
@@ -670,7 +776,7 @@ k_fused(KParams kp, const typename Ty<PREC>::S *__restrict__ fin, const typename
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 const S *gi = gin + (size_t)i * N;
-                gg[i] = dec_g<PREC, D>(gi[n], i, pp);
+                gg[i] = dec_g<PREC, D>(PF ? gr[PF ? i : 0] : gi[n], i, pp);
             }
             if (collide) {
                 const R mup = s_t[t0][NP][tcen];
@@ -1022,7 +1128,7 @@ static int choose_chunk(long long tiles, int planes)
     return (int)c;
 }
 
-template <int D, int PREC, int TX, int TY>
+template <int D, int PREC, int TX, int TY, int NTH>
 static int fused_t(const KParams &kp, const Buffers &b, int pc, int fc, hipStream_t st)
 {
     int ntx = (kp.nx + TX - 1) / TX;
@@ -1030,25 +1136,27 @@ static int fused_t(const KParams &kp, const Buffers &b, int pc, int fc, hipStrea
     int planes = kp.walls ? kp.nw - 2 : kp.nw;
     int chunk = choose_chunk((long long)ntx * nty, planes);
     dim3 grid((unsigned)(ntx * nty), (unsigned)((planes + chunk - 1) / chunk));
-    k_fused<D, PREC, TX, TY><<<grid, TX * TY, 0, st>>>(
+    k_fused<D, PREC, TX, TY, NTH><<<grid, NTH, 0, st>>>(
         kp, (SP<PREC>)b.f[pc], (SP<PREC>)b.g[pc], (SP<PREC>)b.f[1 - pc], (SP<PREC>)b.g[1 - pc],
         (RP<PREC>)b.rho[1 - fc], (RP<PREC>)b.phi[1 - fc], (RP<PREC>)b.rho[fc], (RP<PREC>)b.phi[fc],
         b.counters, chunk);
     return LBM3_CHECK_LAUNCH();
 }
 
+bool fused_fills_ghost(const KParams &kp) { return kp.D == 2; }
+
 int launch_fused(const KParams &kp, int prec, const Buffers &b, int pc, int fc, void *stream)
 {
     hipStream_t st = (hipStream_t)stream;
     if (kp.D == 2) {
         bool small = (long long)kp.nx * kp.nw < (1LL << 20);
-        if (prec == P64) return small ? fused_t<2, P64, 64, 1>(kp, b, pc, fc, st) : fused_t<2, P64, 256, 1>(kp, b, pc, fc, st);
-        if (prec == P32) return small ? fused_t<2, P32, 64, 1>(kp, b, pc, fc, st) : fused_t<2, P32, 256, 1>(kp, b, pc, fc, st);
-        return small ? fused_t<2, P16, 64, 1>(kp, b, pc, fc, st) : fused_t<2, P16, 256, 1>(kp, b, pc, fc, st);
+        if (prec == P64) return small ? fused_t<2, P64, 62, 1, 64>(kp, b, pc, fc, st) : fused_t<2, P64, 254, 1, 256>(kp, b, pc, fc, st);
+        if (prec == P32) return small ? fused_t<2, P32, 62, 1, 64>(kp, b, pc, fc, st) : fused_t<2, P32, 254, 1, 256>(kp, b, pc, fc, st);
+        return small ? fused_t<2, P16, 62, 1, 64>(kp, b, pc, fc, st) : fused_t<2, P16, 254, 1, 256>(kp, b, pc, fc, st);
     }
-    if (prec == P64) return fused_t<3, P64, 32, 4>(kp, b, pc, fc, st);
-    if (prec == P32) return fused_t<3, P32, 32, 8>(kp, b, pc, fc, st);
-    return fused_t<3, P16, 32, 8>(kp, b, pc, fc, st);
+    if (prec == P64) return fused_t<3, P64, 32, 4, 128>(kp, b, pc, fc, st);
+    if (prec == P32) return fused_t<3, P32, 32, 8, 256>(kp, b, pc, fc, st);
+    return fused_t<3, P16, 32, 8, 256>(kp, b, pc, fc, st);
 }
 
 template <int D, int PREC>

@@ -89,7 +89,7 @@ def lib():
         L.lbm3_step.restype = C.c_int
         L.lbm3_step.argtypes = [vp, C.c_int64]
         L.lbm3_step_profiled.restype = C.c_int
-        L.lbm3_step_profiled.argtypes = [vp, C.c_int64, dp]
+        L.lbm3_step_profiled.argtypes = [vp, C.c_int64, C.c_int32, dp]
         L.lbm3_observe.restype = C.c_int
         L.lbm3_observe.argtypes = [vp, C.c_uint32, C.POINTER(lbm3_obs), dp, dp, dp, dp]
         L.lbm3_contact_angle.restype = C.c_int
@@ -181,12 +181,14 @@ def lbm3_step(h, nsteps):
     _check(h, lib().lbm3_step(h, int(nsteps)))
 
 
-def lbm3_step_profiled(h, nsteps):
-    """Run nsteps with events around every launch; returns device ms summed
-    per kernel (moments, ghost, fused) and the span of the whole run."""
-    ms = np.zeros(4)
-    _check(h, lib().lbm3_step_profiled(h, int(nsteps), _dp(ms)))
-    return {"moments": ms[0], "ghost": ms[1], "fused": ms[2], "span": ms[3]}
+def lbm3_step_profiled(h, nsteps, sample_every=1):
+    """Run nsteps with events around the launches of every sample_every-th
+    step; returns the mean device ms per launch of the moments, ghost-layer
+    (0 in 2D) and fused kernels, the span of the whole run in ms and the
+    number of sampled steps."""
+    ms = np.zeros(5)
+    _check(h, lib().lbm3_step_profiled(h, int(nsteps), int(sample_every), _dp(ms)))
+    return {"moments": ms[0], "ghost": ms[1], "fused": ms[2], "span": ms[3], "sampled": int(ms[4])}
 
 
 def lbm3_observe(h, what, rho_out=None, phi_out=None, f_out=None, g_out=None, check=True):
@@ -244,8 +246,8 @@ class Sim:
     def step(self, n=1):
         lbm3_step(self.h, n)
 
-    def step_profiled(self, n):
-        return lbm3_step_profiled(self.h, n)
+    def step_profiled(self, n, sample_every=1):
+        return lbm3_step_profiled(self.h, n, sample_every)
 
     def observe(self):
         st, o = lbm3_observe(self.h, OBS_SUMS)
