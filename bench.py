@@ -31,11 +31,41 @@ def workload_params(L, precision):
                          wetting=L.WET_GEOM_INTERP, theta_deg=THETA, precision=precision)
 
 
+SAMPLE_EVERY = 25  # events around the launches of every 25th step
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_fused_d2q9_2048x64.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1904_06881_amd", "csrc", "lbm3_kernels.hip")
+
+
+def measured_traffic():
+    """HBM bytes per fused launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE per dispatch, scaled by the copy
+    calibration), or None when the kernel source has changed since."""
+    import hashlib
+    try:
+        text = open(PMC_SUMMARY).read()
+        src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    kv = {}
+    for line in text.splitlines():
+        if ":" in line and not line.startswith(" "):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != src:
+        return None
+    try:
+        return 1024.0 * (float(kv["traffic_fetch_kib_per_dispatch"]) * float(kv["fetch_factor"]) +
+                         float(kv["traffic_write_kib_per_dispatch"]) * float(kv["write_factor"]))
+    except (KeyError, ValueError):
+        return None
+
+
 def bytes_per_node(Q, s, sf, fp16):
     """Algorithmic HBM bytes per fluid-node update.  Fused kernel: read and
     write both population sets (4 Q s) and read rho, phi (2 s_f), plus the
     previous step's rho, phi for FP16 decoding.  Moments kernel: read both
-    sets (2 Q s), write rho, phi (2 s_f) (+ decode fields for FP16)."""
+    sets (2 Q s), write rho, phi (2 s_f) (+ decode fields for FP16).  The
+    wall ghost layers (two rows) are left out."""
     extra = 2 * sf if fp16 else 0
     fused = 4 * Q * s + 2 * sf + extra
     moments = 2 * Q * s + 2 * sf + extra
@@ -52,7 +82,7 @@ def run_gpu(L, I, precision, steps, warmup):
     sim.step(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    prof = sim.step_profiled(steps)
+    prof = sim.step_profiled(steps, SAMPLE_EVERY)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     obs = sim.observe()
@@ -90,7 +120,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5000)
     ap.add_argument("--warmup", type=int, default=500)
-    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-variants", action="store_true", help="skip the FP64 / FP16-storage runs")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="only run a plain 256 MiB device copy (HBM counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the build runs a single simulation per device "
@@ -103,6 +136,14 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.copy_calib:
+        x = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4}), flush=True)
+        return
 
     fluid = NX * (NY - 2)
     wall, prof, obs = run_gpu(L, I, L.FP32, args.steps, args.warmup)
@@ -110,22 +151,22 @@ def main():
     mlups = fluid * args.steps / wall / 1e6
 
     fused_b, mom_b, alg_b = bytes_per_node(9, 4, 4, False)
-    kern = {k: prof[k] / args.steps for k in ("moments", "ghost", "fused")}
+    kern = {k: prof[k] for k in ("moments", "fused")}  # mean ms per launch
     dom = max(kern, key=kern.get)
-    per_launch_bytes = {"fused": fused_b * fluid, "moments": mom_b * fluid,
-                        "ghost": 2 * NX * (4 * 4 + 2 * 4)}[dom]
+    per_launch_bytes = {"fused": fused_b * fluid, "moments": mom_b * fluid}[dom]
     achieved = per_launch_bytes / (kern[dom] * 1e-3) / 1e9
-    roof = {"bound": "hbm", "kernel": "k_fused" if dom == "fused" else "k_" + dom,
+    roof = {"bound": "hbm", "kernel": "k_" + dom,
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None, "bytes_per_launch": per_launch_bytes, "avg_launch_ms": kern[dom]}
+            "traffic": measured_traffic() if dom == "fused" else None, "bytes_per_launch": per_launch_bytes, "avg_launch_ms": kern[dom],
+            "launches_timed": prof["sampled"]}
 
     variants = {}
-    for name, prec, b in (("f64", L.FP64, bytes_per_node(9, 8, 8, False)),
-                          ("f16s", L.FP16S, bytes_per_node(9, 2, 4, True))):
+    for name, prec, b in () if args.no_variants else (("f64", L.FP64, bytes_per_node(9, 8, 8, False)),
+                                                      ("f16s", L.FP16S, bytes_per_node(9, 2, 4, True))):
         n = max(200, args.steps // 4)
         w, pr, o = run_gpu(L, I, prec, n, min(args.warmup, 200))
-        variants[name] = {"MLUPS": fluid * n / w / 1e6, "fused_ms": pr["fused"] / n,
-                          "fused_GBs": b[0] * fluid / (pr["fused"] / n * 1e-3) / 1e9,
+        variants[name] = {"MLUPS": fluid * n / w / 1e6, "fused_ms": pr["fused"],
+                          "fused_GBs": b[0] * fluid / (pr["fused"] * 1e-3) / 1e9,
                           "n_bad": o["n_bad"], "alpha_fallback": o["n_fallback"]}
 
     line = {
@@ -135,10 +176,10 @@ def main():
         "config": {"workload": "D2Q9 capillary filling 2048x64, liquid-2 slug x<256, liquid-3 films "
                                "3 rows, density ratio 1000, gamma 0.01, width 4, tau 1, geometric "
                                "interpolation 60 deg, FP32 storage",
-                   "grid": [NX, NY], "fluid_nodes": fluid, "precision": "fp32", "stream_launches_per_step": 3},
+                   "grid": [NX, NY], "fluid_nodes": fluid, "precision": "fp32", "stream_launches_per_step": 2},
         "hbm_frac_of_step": mlups * 1e6 * alg_b / (HBM_PEAK_GBS * 1e9),
         "bytes_per_node_alg": alg_b,
-        "kernel_ms_per_step": kern,
+        "kernel_ms_per_launch": kern,
         "n_bad": obs["n_bad"],
         "alpha_kinds": {"newton": obs["n_newton"], "small_deviation": obs["n_shortcut"],
                         "fallback": obs["n_fallback"]},
