@@ -177,6 +177,86 @@ lbm3_status lbm3_contact_angle(lbm3 *h, int32_t comp, int32_t wall, double exclu
 lbm3_status lbm3_destroy(lbm3 *h);
 const char *lbm3_last_error(const lbm3 *h);
 
+/* ---------------------------------------------------- batched stepping ---
+ * Many simulations advanced in lockstep, every step of all of them one
+ * launch per kernel class (moments, 3D ghost layers, fused update per tile
+ * class and precision), blocks mapped to simulations through a device table.
+ * Each simulation's arithmetic is that of lbm3_step on it alone, so results
+ * are bitwise the same alone and in any batch.  This serves many small grids
+ * that cannot fill the GPU one at a time (Sec. IV's update, batched). */
+
+/* Device bytes of the descriptor image lbm3_step_batch needs for hs[0..n-1]
+ * (*bytes; LBM3_EINVAL for a null, uninitialised or repeated handle). */
+lbm3_status lbm3_batch_workspace(lbm3 *const *hs, int32_t n, size_t *bytes);
+
+/* Advance hs[0..n-1] by nsteps each on `stream` (a hipStream_t; every
+ * handle's own work must already be ordered before it, e.g. created on the
+ * same stream).  ws: device memory of at least lbm3_batch_workspace() bytes,
+ * 256-byte aligned, caller-owned and not reused until the steps are done.
+ * Uploads the image (synchronising the stream once) and enqueues the steps.
+ * LBM3_EINVAL on bad handles, LBM3_ENOMEM for a short workspace,
+ * LBM3_EDEVICE on a failed launch. */
+lbm3_status lbm3_step_batch(lbm3 *const *hs, int32_t n, int64_t nsteps, void *stream, void *ws,
+                            size_t ws_bytes);
+
+/* ------------------------------------------------------------- serving ---
+ * Continuous batching: requests (parameters, initial fields, step count)
+ * queue on the host; each round retires finished simulations, admits queued
+ * ones first-come first-served while their device footprint fits the pool
+ * (later, smaller requests may pass one that does not fit, until it has
+ * waited max_skips rounds) and enqueues up to `quantum` batched steps of
+ * every resident simulation, returning while the GPU works.  Tension
+ * calibration (lbm3_resolve) runs at submission, on the host. */
+typedef struct lbm3_server lbm3_server;
+
+typedef struct {
+    uint64_t tag;           /* the request's tag */
+    int32_t  status;        /* LBM3_OK, or why the request failed */
+    int32_t  has_fields;    /* final rho, phi kept for lbm3_server_fields */
+    int64_t  steps;         /* steps taken */
+    int64_t  nodes;         /* lattice nodes of the request */
+    double   t_submit, t_admit, t_done;  /* seconds on lbm3_server_clock */
+    double   bytes;         /* pool bytes held while resident */
+    lbm3_obs obs;           /* observables of the final state */
+} lbm3_result;
+
+enum { LBM3_SERVE_FIELDS = 1u };  /* keep the final rho, phi (host copy) */
+
+/* Pool bytes a request with these parameters holds while resident (its
+ * lbm3_footprint plus its share of the batch tables); 0 if invalid. */
+size_t lbm3_server_request_bytes(const lbm3_params *p);
+
+/* pool: device memory, 256-byte aligned, owned by the caller and used only
+ * by the server until lbm3_server_destroy; stream: hipStream_t for all of
+ * its work; max_resident >= 1 simulations at once; max_skips >= 0. */
+lbm3_status lbm3_server_create(void *pool, size_t pool_bytes, void *stream, int32_t max_resident,
+                               int32_t max_skips, lbm3_server **out);
+
+/* Queue a request; rho0, phi0 (host, n[0] n[1] n[2] doubles each, x fastest)
+ * are copied.  Parameter or calibration failures, or a footprint beyond the
+ * pool, come back at once as a result with that status (the call itself
+ * returns LBM3_OK); LBM3_EINVAL only for null arguments or nsteps < 0. */
+lbm3_status lbm3_server_submit(lbm3_server *s, const lbm3_params *p, const double *rho0, const double *phi0,
+                               int64_t nsteps, uint64_t tag, uint32_t flags);
+
+/* One round (see above).  Blocks only for the previous round's GPU work.
+ * n_resident, n_queued (may be NULL): simulations on the device / waiting. */
+lbm3_status lbm3_server_run(lbm3_server *s, int64_t quantum, int32_t *n_resident, int32_t *n_queued);
+
+/* Pop the oldest finished result into *out: 1 if one was returned, 0 if none,
+ * negative lbm3_status on bad arguments. */
+int32_t lbm3_server_poll(lbm3_server *s, lbm3_result *out);
+
+/* Copy the kept final fields of result `tag` (n doubles each, may be NULL)
+ * and release them.  LBM3_EINVAL when none are kept for that tag. */
+lbm3_status lbm3_server_fields(lbm3_server *s, uint64_t tag, double *rho_out, double *phi_out);
+
+/* Seconds since the server was created (the clock of lbm3_result). */
+double lbm3_server_clock(const lbm3_server *s);
+
+/* Wait for in-flight work, release every simulation and the server. */
+lbm3_status lbm3_server_destroy(lbm3_server *s);
+
 #ifdef __cplusplus
 }
 #endif

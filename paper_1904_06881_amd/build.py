@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm3.so")
-SOURCES = ["lbm3_kernels.hip", "lbm3_api.hip", "lbm3_params.cpp"]
+SOURCES = ["lbm3_kernels.hip", "lbm3_api.hip", "lbm3_serve.hip", "lbm3_params.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -12,6 +12,7 @@
 
 #include "../../include/lbm3.h"
 #include "lbm3_internal.h"
+#include "lbm3_batch.h"
 #include "lbm3_params.h"
 
 using lbm3k::Buffers;
@@ -505,4 +506,170 @@ const char *lbm3_last_error(const lbm3 *h)
     return h ? h->err.c_str() : g_create_err.c_str();
 }
 
+lbm3_status lbm3_batch_workspace(lbm3 *const *hs, int32_t n, size_t *bytes)
+{
+    if (!bytes) return LBM3_EINVAL;
+    *bytes = lbm3b::image_bytes(hs, n);
+    return *bytes ? LBM3_OK : LBM3_EINVAL;
+}
+
+lbm3_status lbm3_step_batch(lbm3 *const *hs, int32_t n, int64_t nsteps, void *stream, void *ws, size_t ws_bytes)
+{
+    if (nsteps < 0) return LBM3_EINVAL;
+    lbm3b::Image img;
+    lbm3_status st = lbm3b::build(hs, n, img);
+    if (st != LBM3_OK) return st;
+    if (!ws || ws_bytes < img.bytes.size() || ((uintptr_t)ws & 255) != 0) return LBM3_ENOMEM;
+    hipStream_t s = (hipStream_t)stream;
+    // the image is in pageable memory: wait for the copy before it goes
+    if (hipMemcpyAsync(ws, img.bytes.data(), img.bytes.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return LBM3_EDEVICE;
+    return lbm3b::enqueue(hs, n, img, ws, 0, nsteps, s);
+}
+
 }  // extern "C"
+
+// ------------------------------------------------------------- batching --
+namespace lbm3b {
+
+using lbm3k::FusedGeom;
+using lbm3k::SimDesc;
+
+static bool check_handles(lbm3 *const *hs, int n)
+{
+    if (!hs || n < 1) return false;
+    for (int i = 0; i < n; ++i) {
+        if (!hs[i] || !hs[i]->inited) return false;
+        for (int j = 0; j < i; ++j)
+            if (hs[j] == hs[i]) return false;  // one handle twice would step twice
+    }
+    return true;
+}
+
+// launches of the batch: moments per (D, precision), ghost layers per
+// (D, precision) where the step has them, fused per (tile class, precision)
+static void plan(lbm3 *const *hs, int n, std::vector<Launch> &L)
+{
+    auto find = [&](int kind, int D, int prec, int cls) -> Launch & {
+        for (auto &l : L)
+            if (l.kind == kind && l.D == D && l.prec == prec && l.cls == cls) return l;
+        Launch l;
+        l.kind = kind;
+        l.D = D;
+        l.prec = prec;
+        l.cls = cls;
+        l.table_off = 0;
+        l.prefix.push_back(0);
+        L.push_back(l);
+        return L.back();
+    };
+    for (int i = 0; i < n; ++i) {
+        const KParams &k = hs[i]->kp;
+        int prec = hs[i]->prec;
+        Launch &m = find(0, k.D, prec, 0);
+        m.sims.push_back(i);
+        m.prefix.push_back(m.prefix.back() + lbm3k::moments_blocks(k));
+        long long gb = lbm3k::ghost_blocks(k);
+        if (gb > 0) {
+            Launch &g = find(1, k.D, prec, 0);
+            g.sims.push_back(i);
+            g.prefix.push_back(g.prefix.back() + gb);
+        }
+        FusedGeom fg = lbm3k::fused_geometry(k, prec);
+        Launch &f = find(2, k.D, prec, fg.cls);
+        f.sims.push_back(i);
+        f.prefix.push_back(f.prefix.back() + (long long)fg.ntiles * fg.nchunks);
+    }
+    // kernel classes in step order
+    std::stable_sort(L.begin(), L.end(), [](const Launch &a, const Launch &b) { return a.kind < b.kind; });
+}
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+size_t image_bytes(lbm3 *const *hs, int n)
+{
+    if (!check_handles(hs, n)) return 0;
+    std::vector<Launch> L;
+    plan(hs, n, L);
+    size_t bytes = align256(sizeof(SimDesc) * (size_t)n);
+    for (auto &l : L) bytes += align256(sizeof(int) * (size_t)l.prefix.back());
+    return bytes;
+}
+
+lbm3_status build(lbm3 *const *hs, int n, Image &img)
+{
+    if (!check_handles(hs, n)) return LBM3_EINVAL;
+    img.launches.clear();
+    plan(hs, n, img.launches);
+    img.desc_bytes = align256(sizeof(SimDesc) * (size_t)n);
+    size_t off = img.desc_bytes;
+    for (auto &l : img.launches) {
+        l.table_off = off;
+        off += align256(sizeof(int) * (size_t)l.prefix.back());
+    }
+    img.bytes.assign(off, 0);
+    SimDesc *d = (SimDesc *)img.bytes.data();
+    for (int i = 0; i < n; ++i) {
+        const lbm3 *h = hs[i];
+        SimDesc &s = d[i];
+        s.kp = h->kp;
+        for (int j = 0; j < 2; ++j) {
+            s.f[j] = h->b.f[j];
+            s.g[j] = h->b.g[j];
+            s.rho[j] = h->b.rho[j];
+            s.phi[j] = h->b.phi[j];
+        }
+        s.counters = h->b.counters;
+        s.pc = h->pc;
+        s.fc = h->fc;
+        FusedGeom fg = lbm3k::fused_geometry(h->kp, h->prec);
+        s.chunk = fg.chunk;
+        s.ntiles = fg.ntiles;
+        s.fblk0 = s.mblk0 = s.gblk0 = 0;
+    }
+    for (auto &l : img.launches) {
+        int *t = (int *)(img.bytes.data() + l.table_off);
+        for (size_t k = 0; k < l.sims.size(); ++k) {
+            int i = l.sims[k];
+            long long b0 = l.prefix[k], b1 = l.prefix[k + 1];
+            if (b1 > (long long)INT32_MAX) return LBM3_EINVAL;
+            (l.kind == 0 ? d[i].mblk0 : (l.kind == 1 ? d[i].gblk0 : d[i].fblk0)) = (int)b0;
+            for (long long b = b0; b < b1; ++b) t[b] = i;
+        }
+    }
+    return LBM3_OK;
+}
+
+lbm3_status enqueue(lbm3 *const *hs, int m, const Image &img, const void *dev_base, int64_t phase0, int64_t steps,
+                    hipStream_t stream)
+{
+    if (m < 1 || steps < 0) return LBM3_EINVAL;
+    const SimDesc *d = (const SimDesc *)dev_base;
+    const char *base = (const char *)dev_base;
+    for (int64_t t = 0; t < steps; ++t) {
+        const int phase = (int)((phase0 + t) & 1);
+        for (const auto &l : img.launches) {
+            // blocks of the simulations among the first m
+            size_t k = 0;
+            while (k < l.sims.size() && l.sims[k] < m) ++k;
+            long long nb = l.prefix[k];
+            if (nb == 0) continue;
+            const int *tab = (const int *)(base + l.table_off);
+            int r = l.kind == 0 ? lbm3k::launch_moments_batch(l.D, l.prec, d, tab, nb, phase, stream)
+                  : l.kind == 1 ? lbm3k::launch_ghost_batch(l.D, l.prec, d, tab, nb, phase, stream)
+                                : lbm3k::launch_fused_batch(l.cls, l.prec, d, tab, nb, phase, stream);
+            if (r) return LBM3_EDEVICE;
+        }
+    }
+    for (int i = 0; i < m; ++i) {
+        if (steps & 1) {
+            hs[i]->pc ^= 1;
+            hs[i]->fc ^= 1;
+        }
+        hs[i]->step += steps;
+    }
+    return LBM3_OK;
+}
+
+}  // namespace lbm3b

@@ -39,6 +39,23 @@ struct Buffers {
     int n_partials;              // capacity in blocks
 };
 
+// One simulation of a batched launch (device copy written by the host).
+struct SimDesc {
+    KParams kp;
+    void *f[2], *g[2], *rho[2], *phi[2];
+    unsigned long long *counters;
+    int pc, fc;               // buffer parities when the descriptors were written
+    int chunk, ntiles;        // fused launch geometry of this simulation
+    int fblk0, mblk0, gblk0;  // its first block in the fused, moments and ghost launches
+};
+
+// Fused launch geometry of one simulation: tile class (0: 2D 62-node tiles,
+// 1: 2D 254-node tiles, 2: 3D 32x8 tiles (32x4 in FP64)), in-plane tiles,
+// planes per block and blocks along the wall axis.
+struct FusedGeom {
+    int cls, ntiles, chunk, nchunks;
+};
+
 // Launchers (lbm3_kernels.hip).  All asynchronous on `stream`.
 int launch_moments(const KParams &kp, int prec, const Buffers &b, int pc, int fc, void *stream);
 int launch_ghost(const KParams &kp, int prec, const Buffers &b, int fdst, void *stream);
@@ -55,5 +72,17 @@ int launch_export_field(const KParams &kp, int prec, const Buffers &b, int fsrc,
 int launch_contour(const KParams &kp, int prec, const Buffers &b, int fsrc, int comp, int wall,
                    double exclude, void *stream);
 int observe_blocks(const KParams &kp);
+
+// Batched launches over simulations of one class: blocks b = 0..nblocks-1
+// belong to simulation sim[b] of the device descriptor array d.
+FusedGeom fused_geometry(const KParams &kp, int prec);
+long long moments_blocks(const KParams &kp);
+long long ghost_blocks(const KParams &kp);  // 0 when the step has no ghost launch
+int launch_moments_batch(int D, int prec, const SimDesc *d, const int *sim, long long nblocks, int phase,
+                         void *stream);
+int launch_ghost_batch(int D, int prec, const SimDesc *d, const int *sim, long long nblocks, int phase,
+                       void *stream);
+int launch_fused_batch(int cls, int prec, const SimDesc *d, const int *sim, long long nblocks, int phase,
+                       void *stream);
 
 }  // namespace lbm3k

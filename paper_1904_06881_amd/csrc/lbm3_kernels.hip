@@ -264,17 +264,19 @@ __device__ __forceinline__ R entropic_alpha(const R *fp, R *dx, R eps, R tol, in
 }
 
 // -------------------------------------------------------------- moments --
+// rho, phi of fluid node number t (counted from the first fluid plane)
 template <int D, int PREC>
-__global__ void __launch_bounds__(256)
-k_moments(KParams kp, const typename Ty<PREC>::S *__restrict__ f, const typename Ty<PREC>::S *__restrict__ g,
-          const typename Ty<PREC>::R *__restrict__ rprev, const typename Ty<PREC>::R *__restrict__ pprev,
-          typename Ty<PREC>::R *__restrict__ rho, typename Ty<PREC>::R *__restrict__ phi)
+__device__ __forceinline__ void moments_node(const KParams &kp, const typename Ty<PREC>::S *__restrict__ f,
+                                             const typename Ty<PREC>::S *__restrict__ g,
+                                             const typename Ty<PREC>::R *__restrict__ rprev,
+                                             const typename Ty<PREC>::R *__restrict__ pprev,
+                                             typename Ty<PREC>::R *__restrict__ rho,
+                                             typename Ty<PREC>::R *__restrict__ phi, long long t)
 {
     using R = typename Ty<PREC>::R;
     constexpr int Q = D == 2 ? 9 : 27;
     long long first = kp.walls ? kp.PS : 0;
     long long count = kp.walls ? kp.N - 2 * kp.PS : kp.N;
-    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= count) return;
     long long n = first + t;
     R rp = (R)0, pp = (R)0;
@@ -287,6 +289,31 @@ k_moments(KParams kp, const typename Ty<PREC>::S *__restrict__ f, const typename
     }
     rho[n] = r;
     phi[n] = ph;
+}
+
+template <int D, int PREC>
+__global__ void __launch_bounds__(256)
+k_moments(KParams kp, const typename Ty<PREC>::S *__restrict__ f, const typename Ty<PREC>::S *__restrict__ g,
+          const typename Ty<PREC>::R *__restrict__ rprev, const typename Ty<PREC>::R *__restrict__ pprev,
+          typename Ty<PREC>::R *__restrict__ rho, typename Ty<PREC>::R *__restrict__ phi)
+{
+    moments_node<D, PREC>(kp, f, g, rprev, pprev, rho, phi, (long long)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// One launch over many simulations: block b belongs to simulation sim[b];
+// `phase` is the number of steps taken since the descriptors were written.
+template <int D, int PREC>
+__global__ void __launch_bounds__(256)
+k_moments_batch(const SimDesc *__restrict__ d, const int *__restrict__ sim, int phase)
+{
+    using R = typename Ty<PREC>::R;
+    using S = typename Ty<PREC>::S;
+    const SimDesc &sd = d[sim[blockIdx.x]];
+    const KParams &kp = sd.kp;
+    const int pc = sd.pc ^ phase, fc = sd.fc ^ phase;
+    moments_node<D, PREC>(kp, (const S *)sd.f[pc], (const S *)sd.g[pc], (const R *)sd.rho[fc], (const R *)sd.phi[fc],
+                          (R *)sd.rho[1 - fc], (R *)sd.phi[1 - fc],
+                          (long long)(blockIdx.x - sd.mblk0) * blockDim.x + threadIdx.x);
 }
 
 // ----------------------------------------------------------- ghost layers
@@ -409,12 +436,10 @@ __device__ __forceinline__ void ghost_value(const KParams &kp, int wall, Get get
 }
 
 template <int D, typename R>
-__global__ void __launch_bounds__(256)
-k_ghost(KParams kp, R *__restrict__ rho, R *__restrict__ phi)
+__device__ __forceinline__ void ghost_node(const KParams &kp, R *__restrict__ rho, R *__restrict__ phi, int t)
 {
     int nx = kp.nx, ny = kp.ny;
     int np = (D == 2) ? nx : nx * ny;  // ghost nodes per wall
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= 2 * np) return;
     int wall = t / np;
     int k = t % np;
@@ -430,6 +455,23 @@ k_ghost(KParams kp, R *__restrict__ rho, R *__restrict__ phi)
     ghost_value<D, R>(kp, wall, get, out_r, out_p);
     rho[ng] = out_r;
     phi[ng] = out_p;
+}
+
+template <int D, typename R>
+__global__ void __launch_bounds__(256)
+k_ghost(KParams kp, R *__restrict__ rho, R *__restrict__ phi)
+{
+    ghost_node<D, R>(kp, rho, phi, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+template <int D, typename R>
+__global__ void __launch_bounds__(256)
+k_ghost_batch(const SimDesc *__restrict__ d, const int *__restrict__ sim, int phase)
+{
+    const SimDesc &sd = d[sim[blockIdx.x]];
+    const KParams &kp = sd.kp;
+    const int fc = sd.fc ^ phase;
+    ghost_node<D, R>(kp, (R *)sd.rho[1 - fc], (R *)sd.phi[1 - fc], (blockIdx.x - sd.gblk0) * blockDim.x + threadIdx.x);
 }
 
 // ---------------------------------------------------------------- fused --
@@ -450,13 +492,12 @@ __device__ __forceinline__ int wrapl(int v, int n)
 // back for their own nodes), so a step is the moments kernel and this one;
 // in 3D the ghost-layer kernel runs in between.
 template <int D, int PREC, int TX, int TY, int NTH>
-__global__ void __launch_bounds__(NTH)
-__attribute__((amdgpu_waves_per_eu(D == 3 ? (PREC == P64 ? 1 : 2) : (PREC == P64 ? 2 : (NTH <= 64 ? 3 : 4)))))
-k_fused(KParams kp, const typename Ty<PREC>::S *__restrict__ fin, const typename Ty<PREC>::S *__restrict__ gin,
-        typename Ty<PREC>::S *__restrict__ fout, typename Ty<PREC>::S *__restrict__ gout,
-        typename Ty<PREC>::R *__restrict__ rho, typename Ty<PREC>::R *__restrict__ phi,
-        const typename Ty<PREC>::R *__restrict__ rprev, const typename Ty<PREC>::R *__restrict__ pprev,
-        unsigned long long *__restrict__ cnt, int chunk)
+__device__ __forceinline__ void
+fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, const typename Ty<PREC>::S *__restrict__ gin,
+           typename Ty<PREC>::S *__restrict__ fout, typename Ty<PREC>::S *__restrict__ gout,
+           typename Ty<PREC>::R *__restrict__ rho, typename Ty<PREC>::R *__restrict__ phi,
+           const typename Ty<PREC>::R *__restrict__ rprev, const typename Ty<PREC>::R *__restrict__ pprev,
+           unsigned long long *__restrict__ cnt, int chunk, int bx, int by)
 {
     using R = typename Ty<PREC>::R;
     using S = typename Ty<PREC>::S;
@@ -477,10 +518,10 @@ k_fused(KParams kp, const typename Ty<PREC>::S *__restrict__ fin, const typename
     const int nx = kp.nx, ny = kp.ny, nw = kp.nw;
     const unsigned N = (unsigned)kp.N, PS = (unsigned)kp.PS;
     const int ntx = (nx + TX - 1) / TX;
-    const int x0 = (blockIdx.x % ntx) * TX;
-    const int y0 = (D == 3) ? (blockIdx.x / ntx) * TY : 0;
+    const int x0 = (bx % ntx) * TX;
+    const int y0 = (D == 3) ? (bx / ntx) * TY : 0;
     const int pf0 = kp.walls ? 1 : 0, pf1 = kp.walls ? nw - 1 : nw;
-    const int pb = pf0 + blockIdx.y * chunk;
+    const int pb = pf0 + by * chunk;
     const int pe = min(pb + chunk, pf1);
     if (pb >= pe) return;
     if (tid < 3) s_cnt[tid] = 0;
@@ -824,6 +865,38 @@ k_fused(KParams kp, const typename Ty<PREC>::S *__restrict__ fin, const typename
     if (tid < 3 && s_cnt[tid]) atomicAdd(&cnt[tid], (unsigned long long)s_cnt[tid]);
 }
 
+#define LBM3_FUSED_ATTR                                                                                     \
+    __launch_bounds__(NTH)                                                                                  \
+    __attribute__((amdgpu_waves_per_eu(D == 3 ? (PREC == P64 ? 1 : 2) : (PREC == P64 ? 2 : (NTH <= 64 ? 3 : 4)))))
+
+template <int D, int PREC, int TX, int TY, int NTH>
+__global__ void LBM3_FUSED_ATTR
+k_fused(KParams kp, const typename Ty<PREC>::S *__restrict__ fin, const typename Ty<PREC>::S *__restrict__ gin,
+        typename Ty<PREC>::S *__restrict__ fout, typename Ty<PREC>::S *__restrict__ gout,
+        typename Ty<PREC>::R *__restrict__ rho, typename Ty<PREC>::R *__restrict__ phi,
+        const typename Ty<PREC>::R *__restrict__ rprev, const typename Ty<PREC>::R *__restrict__ pprev,
+        unsigned long long *__restrict__ cnt, int chunk)
+{
+    fused_tile<D, PREC, TX, TY, NTH>(kp, fin, gin, fout, gout, rho, phi, rprev, pprev, cnt, chunk, blockIdx.x,
+                                     blockIdx.y);
+}
+
+template <int D, int PREC, int TX, int TY, int NTH>
+__global__ void LBM3_FUSED_ATTR
+k_fused_batch(const SimDesc *__restrict__ d, const int *__restrict__ sim, int phase)
+{
+    using R = typename Ty<PREC>::R;
+    using S = typename Ty<PREC>::S;
+    const SimDesc &sd = d[sim[blockIdx.x]];
+    const KParams &kp = sd.kp;
+    const int pc = sd.pc ^ phase, fc = sd.fc ^ phase;
+    const int local = blockIdx.x - sd.fblk0;
+    fused_tile<D, PREC, TX, TY, NTH>(kp, (const S *)sd.f[pc], (const S *)sd.g[pc], (S *)sd.f[1 - pc], (S *)sd.g[1 - pc],
+                                     (R *)sd.rho[1 - fc], (R *)sd.phi[1 - fc], (const R *)sd.rho[fc],
+                                     (const R *)sd.phi[fc], sd.counters, sd.chunk, local % sd.ntiles,
+                                     local / sd.ntiles);
+}
+
 // ---------------------------------------------------------------- init ---
 template <typename R>
 __global__ void __launch_bounds__(256)
@@ -1128,18 +1201,42 @@ static int choose_chunk(long long tiles, int planes)
     return (int)c;
 }
 
+static void tile_of_class(int cls, int prec, int &TX, int &TY)
+{
+    if (cls == 0) { TX = 62; TY = 1; }
+    else if (cls == 1) { TX = 254; TY = 1; }
+    else { TX = 32; TY = prec == P64 ? 4 : 8; }
+}
+
+static int fused_class(const KParams &kp)
+{
+    return kp.D == 3 ? 2 : ((long long)kp.nx * kp.nw < (1LL << 20) ? 0 : 1);
+}
+
+FusedGeom fused_geometry(const KParams &kp, int prec)
+{
+    FusedGeom g;
+    g.cls = fused_class(kp);
+    int TX, TY;
+    tile_of_class(g.cls, prec, TX, TY);
+    int ntx = (kp.nx + TX - 1) / TX;
+    int nty = kp.D == 3 ? (kp.ny + TY - 1) / TY : 1;
+    int planes = kp.walls ? kp.nw - 2 : kp.nw;
+    g.ntiles = ntx * nty;
+    g.chunk = choose_chunk((long long)g.ntiles, planes);
+    g.nchunks = (planes + g.chunk - 1) / g.chunk;
+    return g;
+}
+
 template <int D, int PREC, int TX, int TY, int NTH>
 static int fused_t(const KParams &kp, const Buffers &b, int pc, int fc, hipStream_t st)
 {
-    int ntx = (kp.nx + TX - 1) / TX;
-    int nty = D == 3 ? (kp.ny + TY - 1) / TY : 1;
-    int planes = kp.walls ? kp.nw - 2 : kp.nw;
-    int chunk = choose_chunk((long long)ntx * nty, planes);
-    dim3 grid((unsigned)(ntx * nty), (unsigned)((planes + chunk - 1) / chunk));
+    FusedGeom g = fused_geometry(kp, PREC);
+    dim3 grid((unsigned)g.ntiles, (unsigned)g.nchunks);
     k_fused<D, PREC, TX, TY, NTH><<<grid, NTH, 0, st>>>(
         kp, (SP<PREC>)b.f[pc], (SP<PREC>)b.g[pc], (SP<PREC>)b.f[1 - pc], (SP<PREC>)b.g[1 - pc],
         (RP<PREC>)b.rho[1 - fc], (RP<PREC>)b.phi[1 - fc], (RP<PREC>)b.rho[fc], (RP<PREC>)b.phi[fc],
-        b.counters, chunk);
+        b.counters, g.chunk);
     return LBM3_CHECK_LAUNCH();
 }
 
@@ -1148,15 +1245,90 @@ bool fused_fills_ghost(const KParams &kp) { return kp.D == 2; }
 int launch_fused(const KParams &kp, int prec, const Buffers &b, int pc, int fc, void *stream)
 {
     hipStream_t st = (hipStream_t)stream;
-    if (kp.D == 2) {
-        bool small = (long long)kp.nx * kp.nw < (1LL << 20);
-        if (prec == P64) return small ? fused_t<2, P64, 62, 1, 64>(kp, b, pc, fc, st) : fused_t<2, P64, 254, 1, 256>(kp, b, pc, fc, st);
-        if (prec == P32) return small ? fused_t<2, P32, 62, 1, 64>(kp, b, pc, fc, st) : fused_t<2, P32, 254, 1, 256>(kp, b, pc, fc, st);
-        return small ? fused_t<2, P16, 62, 1, 64>(kp, b, pc, fc, st) : fused_t<2, P16, 254, 1, 256>(kp, b, pc, fc, st);
+    const int cls = fused_class(kp);
+    if (cls == 0) {
+        if (prec == P64) return fused_t<2, P64, 62, 1, 64>(kp, b, pc, fc, st);
+        if (prec == P32) return fused_t<2, P32, 62, 1, 64>(kp, b, pc, fc, st);
+        return fused_t<2, P16, 62, 1, 64>(kp, b, pc, fc, st);
+    }
+    if (cls == 1) {
+        if (prec == P64) return fused_t<2, P64, 254, 1, 256>(kp, b, pc, fc, st);
+        if (prec == P32) return fused_t<2, P32, 254, 1, 256>(kp, b, pc, fc, st);
+        return fused_t<2, P16, 254, 1, 256>(kp, b, pc, fc, st);
     }
     if (prec == P64) return fused_t<3, P64, 32, 4, 128>(kp, b, pc, fc, st);
     if (prec == P32) return fused_t<3, P32, 32, 8, 256>(kp, b, pc, fc, st);
     return fused_t<3, P16, 32, 8, 256>(kp, b, pc, fc, st);
+}
+
+// ------------------------------------------------------- batched launches
+long long moments_blocks(const KParams &kp)
+{
+    long long count = kp.walls ? kp.N - 2 * kp.PS : kp.N;
+    return (count + 255) / 256;
+}
+
+long long ghost_blocks(const KParams &kp)
+{
+    if (!kp.walls || fused_fills_ghost(kp)) return 0;
+    long long np = kp.D == 2 ? kp.nx : (long long)kp.nx * kp.ny;
+    return (2 * np + 255) / 256;
+}
+
+int launch_moments_batch(int D, int prec, const SimDesc *d, const int *sim, long long nblocks, int phase,
+                         void *stream)
+{
+    if (nblocks <= 0) return 0;
+    hipStream_t st = (hipStream_t)stream;
+    dim3 grid((unsigned)nblocks);
+    if (D == 2) {
+        if (prec == P64) k_moments_batch<2, P64><<<grid, 256, 0, st>>>(d, sim, phase);
+        else if (prec == P32) k_moments_batch<2, P32><<<grid, 256, 0, st>>>(d, sim, phase);
+        else k_moments_batch<2, P16><<<grid, 256, 0, st>>>(d, sim, phase);
+    } else {
+        if (prec == P64) k_moments_batch<3, P64><<<grid, 256, 0, st>>>(d, sim, phase);
+        else if (prec == P32) k_moments_batch<3, P32><<<grid, 256, 0, st>>>(d, sim, phase);
+        else k_moments_batch<3, P16><<<grid, 256, 0, st>>>(d, sim, phase);
+    }
+    return LBM3_CHECK_LAUNCH();
+}
+
+int launch_ghost_batch(int D, int prec, const SimDesc *d, const int *sim, long long nblocks, int phase,
+                       void *stream)
+{
+    if (nblocks <= 0) return 0;
+    hipStream_t st = (hipStream_t)stream;
+    dim3 grid((unsigned)nblocks);
+    if (D == 2) {
+        if (prec == P64) k_ghost_batch<2, double><<<grid, 256, 0, st>>>(d, sim, phase);
+        else k_ghost_batch<2, float><<<grid, 256, 0, st>>>(d, sim, phase);
+    } else {
+        if (prec == P64) k_ghost_batch<3, double><<<grid, 256, 0, st>>>(d, sim, phase);
+        else k_ghost_batch<3, float><<<grid, 256, 0, st>>>(d, sim, phase);
+    }
+    return LBM3_CHECK_LAUNCH();
+}
+
+int launch_fused_batch(int cls, int prec, const SimDesc *d, const int *sim, long long nblocks, int phase,
+                       void *stream)
+{
+    if (nblocks <= 0) return 0;
+    hipStream_t st = (hipStream_t)stream;
+    dim3 grid((unsigned)nblocks);
+    if (cls == 0) {
+        if (prec == P64) k_fused_batch<2, P64, 62, 1, 64><<<grid, 64, 0, st>>>(d, sim, phase);
+        else if (prec == P32) k_fused_batch<2, P32, 62, 1, 64><<<grid, 64, 0, st>>>(d, sim, phase);
+        else k_fused_batch<2, P16, 62, 1, 64><<<grid, 64, 0, st>>>(d, sim, phase);
+    } else if (cls == 1) {
+        if (prec == P64) k_fused_batch<2, P64, 254, 1, 256><<<grid, 256, 0, st>>>(d, sim, phase);
+        else if (prec == P32) k_fused_batch<2, P32, 254, 1, 256><<<grid, 256, 0, st>>>(d, sim, phase);
+        else k_fused_batch<2, P16, 254, 1, 256><<<grid, 256, 0, st>>>(d, sim, phase);
+    } else {
+        if (prec == P64) k_fused_batch<3, P64, 32, 4, 128><<<grid, 128, 0, st>>>(d, sim, phase);
+        else if (prec == P32) k_fused_batch<3, P32, 32, 8, 256><<<grid, 256, 0, st>>>(d, sim, phase);
+        else k_fused_batch<3, P16, 32, 8, 256><<<grid, 256, 0, st>>>(d, sim, phase);
+    }
+    return LBM3_CHECK_LAUNCH();
 }
 
 template <int D, int PREC>

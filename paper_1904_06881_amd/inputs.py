@@ -159,3 +159,50 @@ def random_fields(shape, seed=0, rho_l=1.0, rho_g=1e-3, chi=5.0, smooth=2):
         c = acc / (1 + 2 * (c.ndim - 1))
     c /= c.sum(axis=0, keepdims=True)
     return fields_from_conc(c[1], c[2], rho_l=rho_l, rho_g=rho_g, chi=chi)
+
+
+def serving_requests(n=512, seed=0, rate=64.0, frac_2d=0.7, grid2=(64, 1024), grid3=(64, 192),
+                     steps=(5000, 20000), theta=(30.0, 150.0), gamma=(0.005, 0.03), precisions=("fp32", "fp16s"),
+                     margin=0.9):
+    """A seeded stream of sessile-drop requests for the serving loop.
+
+    Arrivals are a Poisson process of `rate` per second; a fraction frac_2d
+    are D2Q9 square grids with side log-uniform in grid2, the rest D3Q27 cubes
+    with side log-uniform in grid3; contact angle uniform in theta (all wall
+    angles), step count uniform in `steps`, storage precision uniform over
+    `precisions`, and the three tensions uniform in `gamma` subject to the
+    triangle inequality gamma_ij < margin (gamma_ik + gamma_jk) (redrawn
+    otherwise: outside it one liquid spreads over the other interface and no
+    pairwise calibration exists).  The drop (liquid 2) has radius a quarter
+    of the side.  Returns a list of dicts ordered by arrival time."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t = 0.0
+    out = []
+    for k in range(n):
+        t += rng.exponential(1.0 / rate)
+        two_d = rng.random() < frac_2d
+        lo, hi = grid2 if two_d else grid3
+        side = int(round(np.exp(rng.uniform(np.log(lo), np.log(hi)))))
+        while True:
+            g = rng.uniform(gamma[0], gamma[1], 3)
+            if g[0] < margin * (g[1] + g[2]) and g[1] < margin * (g[0] + g[2]) and g[2] < margin * (g[0] + g[1]):
+                break
+        out.append({
+            "tag": k, "arrival": t, "lattice": "D2Q9" if two_d else "D3Q27",
+            "n": (side, side) if two_d else (side, side, side),
+            "theta": float(rng.uniform(theta[0], theta[1])),
+            "gamma": tuple(float(v) for v in g),
+            "nsteps": int(rng.integers(steps[0], steps[1] + 1)),
+            "precision": precisions[int(rng.integers(0, len(precisions)))],
+            "radius": side / 4.0,
+        })
+    return out
+
+
+def request_fields(req):
+    """Initial rho, phi of a serving request: a liquid-2 sessile drop on the
+    bottom wall, centred along the wall."""
+    n = req["n"]
+    if len(n) == 2:
+        return sessile_drop_2d(n[0], n[1], req["radius"])
+    return sessile_drop_3d(n[0], n[1], n[2], req["radius"])

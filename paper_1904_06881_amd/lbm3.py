@@ -55,9 +55,23 @@ class lbm3_obs(C.Structure):
     ]
 
 
+class lbm3_result(C.Structure):
+    _fields_ = [
+        ("tag", C.c_uint64), ("status", C.c_int32), ("has_fields", C.c_int32),
+        ("steps", C.c_int64), ("nodes", C.c_int64),
+        ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double),
+        ("bytes", C.c_double), ("obs", lbm3_obs),
+    ]
+
+
+SERVE_FIELDS = 1
+
 EXPORTS = ["lbm3_footprint", "lbm3_resolve", "lbm3_create", "lbm3_init", "lbm3_step",
            "lbm3_step_profiled", "lbm3_observe", "lbm3_contact_angle", "lbm3_destroy",
-           "lbm3_last_error"]
+           "lbm3_last_error", "lbm3_batch_workspace", "lbm3_step_batch",
+           "lbm3_server_request_bytes", "lbm3_server_create", "lbm3_server_submit",
+           "lbm3_server_run", "lbm3_server_poll", "lbm3_server_fields", "lbm3_server_clock",
+           "lbm3_server_destroy"]
 
 
 class Lbm3Error(RuntimeError):
@@ -98,6 +112,26 @@ def lib():
         L.lbm3_destroy.argtypes = [vp]
         L.lbm3_last_error.restype = C.c_char_p
         L.lbm3_last_error.argtypes = [vp]
+        L.lbm3_batch_workspace.restype = C.c_int
+        L.lbm3_batch_workspace.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(C.c_size_t)]
+        L.lbm3_step_batch.restype = C.c_int
+        L.lbm3_step_batch.argtypes = [C.POINTER(vp), C.c_int32, C.c_int64, vp, vp, C.c_size_t]
+        L.lbm3_server_request_bytes.restype = C.c_size_t
+        L.lbm3_server_request_bytes.argtypes = [C.POINTER(lbm3_params)]
+        L.lbm3_server_create.restype = C.c_int
+        L.lbm3_server_create.argtypes = [vp, C.c_size_t, vp, C.c_int32, C.c_int32, C.POINTER(vp)]
+        L.lbm3_server_submit.restype = C.c_int
+        L.lbm3_server_submit.argtypes = [vp, C.POINTER(lbm3_params), dp, dp, C.c_int64, C.c_uint64, C.c_uint32]
+        L.lbm3_server_run.restype = C.c_int
+        L.lbm3_server_run.argtypes = [vp, C.c_int64, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.lbm3_server_poll.restype = C.c_int32
+        L.lbm3_server_poll.argtypes = [vp, C.POINTER(lbm3_result)]
+        L.lbm3_server_fields.restype = C.c_int
+        L.lbm3_server_fields.argtypes = [vp, C.c_uint64, dp, dp]
+        L.lbm3_server_clock.restype = C.c_double
+        L.lbm3_server_clock.argtypes = [vp]
+        L.lbm3_server_destroy.restype = C.c_int
+        L.lbm3_server_destroy.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -270,3 +304,100 @@ class Sim:
 
     def contact_angle(self, comp=2, wall=0, exclude=8.0):
         return lbm3_contact_angle(self.h, comp, wall, exclude)
+
+
+def _obs_dict(o):
+    return {"mass": list(o.mass), "rho_sum": o.rho_sum, "phi_sum": o.phi_sum, "mom": list(o.mom),
+            "kinetic": o.kinetic, "umax": o.umax, "n_bad": o.n_bad, "n_newton": o.n_newton,
+            "n_shortcut": o.n_shortcut, "n_fallback": o.n_fallback, "step": o.step}
+
+
+def step_batch(sims, nsteps, stream=None):
+    """Advance the Sim objects `sims` (same device) by nsteps each with
+    batched launches (lbm3_step_batch) on `stream` (default: the first
+    simulation's stream)."""
+    import torch
+    n = len(sims)
+    hs = (C.c_void_p * n)(*[s.h for s in sims])
+    nb = C.c_size_t()
+    st = lib().lbm3_batch_workspace(hs, n, C.byref(nb))
+    if st != 0:
+        raise Lbm3Error(st, "bad batch")
+    ws = torch.empty(nb.value + 256, dtype=torch.uint8, device=sims[0].device)
+    base = (ws.data_ptr() + 255) & ~255
+    stream = stream if stream is not None else sims[0].stream
+    st = lib().lbm3_step_batch(hs, n, int(nsteps), C.c_void_p(stream.cuda_stream), C.c_void_p(base), nb.value)
+    if st != 0:
+        raise Lbm3Error(st, "batched step failed")
+    return ws  # keep alive until the work is done
+
+
+def server_request_bytes(p):
+    return lib().lbm3_server_request_bytes(C.byref(p))
+
+
+class Server:
+    """Continuous-batching request loop (lbm3_server_*) over a device pool of
+    pool_bytes held in a torch tensor, on the current (or given) stream."""
+
+    def __init__(self, pool_bytes, device="cuda:0", max_resident=64, max_skips=4, stream=None):
+        import torch
+        self.device = torch.device(device)
+        self.pool = torch.empty(int(pool_bytes) + 256, dtype=torch.uint8, device=self.device)
+        base = (self.pool.data_ptr() + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        st = lib().lbm3_server_create(C.c_void_p(base), int(pool_bytes), C.c_void_p(self.stream.cuda_stream),
+                                      int(max_resident), int(max_skips), C.byref(h))
+        if st != 0:
+            raise Lbm3Error(st, "server create failed")
+        self.h = h
+        self.shapes = {}
+
+    def submit(self, p, rho0, phi0, nsteps, tag, keep_fields=False):
+        r = np.ascontiguousarray(rho0, dtype=np.float64).reshape(-1)
+        ph = np.ascontiguousarray(phi0, dtype=np.float64).reshape(-1)
+        self.shapes[int(tag)] = np.shape(rho0)
+        st = lib().lbm3_server_submit(self.h, C.byref(p), _dp(r), _dp(ph), int(nsteps), int(tag),
+                                      SERVE_FIELDS if keep_fields else 0)
+        if st != 0:
+            raise Lbm3Error(st, "submit failed")
+
+    def run(self, quantum):
+        nr, nq = C.c_int32(), C.c_int32()
+        st = lib().lbm3_server_run(self.h, int(quantum), C.byref(nr), C.byref(nq))
+        if st != 0:
+            raise Lbm3Error(st, "server round failed")
+        return nr.value, nq.value
+
+    def poll(self):
+        out = []
+        r = lbm3_result()
+        while lib().lbm3_server_poll(self.h, C.byref(r)) == 1:
+            out.append({"tag": r.tag, "status": r.status, "has_fields": bool(r.has_fields), "steps": r.steps,
+                        "nodes": r.nodes, "t_submit": r.t_submit, "t_admit": r.t_admit, "t_done": r.t_done,
+                        "bytes": r.bytes, "obs": _obs_dict(r.obs)})
+        return out
+
+    def fields(self, tag):
+        shape = self.shapes[int(tag)]
+        rho = np.empty(shape)
+        phi = np.empty(shape)
+        st = lib().lbm3_server_fields(self.h, int(tag), _dp(rho), _dp(phi))
+        if st != 0:
+            raise Lbm3Error(st, "no kept fields for tag %d" % tag)
+        return rho, phi
+
+    def clock(self):
+        return lib().lbm3_server_clock(self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().lbm3_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

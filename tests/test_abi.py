@@ -15,14 +15,14 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def declared_symbols():
     src = open(os.path.join(ROOT, "include", "lbm3.h")).read()
-    decl = r"^\s*(?:size_t|lbm3_status|const\s+char\s*\*)\s*(lbm3_[a-z_]+)\s*\("
+    decl = r"^\s*(?:size_t|lbm3_status|int32_t|double|const\s+char\s*\*)\s*(lbm3_[a-z_]+)\s*\("
     return sorted(set(re.findall(decl, src, flags=re.M)))
 
 
 def test_library_exports_every_declared_symbol():
     lib = L.lib()
     names = declared_symbols()
-    assert len(names) >= 9
+    assert len(names) >= 20
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(L.EXPORTS)
@@ -103,3 +103,30 @@ def test_calibration_rejects_impossible_tensions():
     with pytest.raises(L.Lbm3Error) as e:
         L.lbm3_resolve(p)
     assert e.value.status == -6
+
+
+def test_server_request_bytes_cover_the_footprint():
+    """A request holds its lbm3_footprint plus a share of the batch tables;
+    invalid parameters hold nothing."""
+    p = L.make_params(L.D2Q9, (256, 128), lam=(0.07, 0.03, 0.03), kap=(0.03, 0.03, 0.03), precision=L.FP32)
+    fp = L.lbm3_footprint(p)
+    rb = L.server_request_bytes(p)
+    assert fp < rb < fp + 64 * 1024 + 256 * 128 // 16
+    p3 = L.make_params(L.D3Q27, (64, 64, 64), lam=(0.07, 0.03, 0.03), kap=(0.03, 0.03, 0.03), precision=L.FP16S)
+    assert L.server_request_bytes(p3) > L.lbm3_footprint(p3)
+    bad = L.make_params(7, (8, 8), lam=(1, 1, 1), kap=(1, 1, 1))
+    assert L.server_request_bytes(bad) == 0
+
+
+def test_batch_and_server_reject_bad_arguments_without_a_gpu():
+    """Argument checks that return before any device call."""
+    lib = L.lib()
+    nb = ctypes.c_size_t(7)
+    assert lib.lbm3_batch_workspace(None, 0, ctypes.byref(nb)) == -1
+    assert lib.lbm3_step_batch(None, 0, 1, None, None, 0) == -1
+    h = ctypes.c_void_p()
+    assert lib.lbm3_server_create(None, 1 << 30, None, 4, 0, ctypes.byref(h)) == -1
+    assert lib.lbm3_server_create(ctypes.c_void_p(256), 1 << 30, None, 0, 0, ctypes.byref(h)) == -1
+    assert lib.lbm3_server_run(None, 1, None, None) == -1
+    assert lib.lbm3_server_poll(None, None) == -1
+    assert lib.lbm3_server_destroy(None) == -1
