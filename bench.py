@@ -17,6 +17,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -90,6 +92,94 @@ def run_gpu(L, I, precision, steps, warmup):
     return wall, prof, obs
 
 
+# Serving sample: 48 requests of the serving stream (Poisson arrivals at 16
+# per second; 70% D2Q9 squares 64..1024, 30% D3Q27 cubes 64..192; contact
+# angle 30..150 deg; tensions 0.005..0.03; FP32 or FP16-offset storage) with
+# the step counts of the full stream (5k..20k) divided by 20.
+SERVE_N, SERVE_RATE, SERVE_STEPS, SERVE_QUANTUM = 48, 16.0, (250, 1000), 50
+SERVE_POOL = 24 << 30
+
+
+def serving_requests(L, I):
+    reqs = I.serving_requests(SERVE_N, seed=2024, rate=SERVE_RATE, steps=SERVE_STEPS)
+    for q in reqs:
+        lat = L.D2Q9 if q["lattice"] == "D2Q9" else L.D3Q27
+        prec = L.FP32 if q["precision"] == "fp32" else L.FP16S
+        q["params"] = L.make_params(lat, q["n"], gamma=q["gamma"], theta_deg=q["theta"], precision=prec)
+        q["fields"] = I.request_fields(q)
+        q["updates"] = float(np.prod(q["n"])) * q["nsteps"]
+    return reqs
+
+
+def _pct(v, q):
+    return float(np.percentile(np.asarray(v), q)) if len(v) else None
+
+
+def run_serving(L, reqs):
+    """Continuous batching: submit each request at its arrival time, run
+    rounds of SERVE_QUANTUM batched steps, collect results.  Time to result
+    is completion minus scheduled arrival."""
+    srv = L.Server(SERVE_POOL, max_resident=64, max_skips=4)
+    t0 = srv.clock()
+    done, i, n = {}, 0, len(reqs)
+    while len(done) < n:
+        now = srv.clock() - t0
+        while i < n and reqs[i]["arrival"] <= now:
+            q = reqs[i]
+            srv.submit(q["params"], *q["fields"], q["nsteps"], tag=q["tag"])
+            i += 1
+        nr, nq = srv.run(SERVE_QUANTUM)
+        for r in srv.poll():
+            done[r["tag"]] = r
+        if nr == 0 and nq == 0 and i < n and len(done) == i:
+            time.sleep(max(0.0, reqs[i]["arrival"] - (srv.clock() - t0)))
+    makespan = max(r["t_done"] for r in done.values()) - t0
+    srv.close()
+    lat = [done[q["tag"]]["t_done"] - t0 - q["arrival"] for q in reqs]
+    ok = sum(1 for r in done.values() if r["status"] == 0)
+    return lat, makespan, ok
+
+
+def run_plain(L, reqs):
+    """The same stream solved one request at a time (first come first
+    served), each alone on the GPU with lbm3_step."""
+    import torch
+    t0 = time.perf_counter()
+    lat, ok = [], 0
+    for q in reqs:
+        now = time.perf_counter() - t0
+        if q["arrival"] > now:
+            time.sleep(q["arrival"] - now)
+        s = L.Sim(q["params"])
+        s.init(*q["fields"])
+        s.step(q["nsteps"])
+        o = s.observe()
+        s.close()
+        del s
+        ok += o["status"] == 0
+        lat.append(time.perf_counter() - t0 - q["arrival"])
+    torch.cuda.synchronize()
+    return lat, time.perf_counter() - t0, ok
+
+
+def serving_leg(L, I):
+    reqs = serving_requests(L, I)
+    total = sum(q["updates"] for q in reqs)
+    lat_s, span_s, ok_s = run_serving(L, reqs)
+    lat_p, span_p, ok_p = run_plain(L, reqs)
+    return {
+        "workload": "%d requests of the serving stream (seed 2024): Poisson arrivals %.0f/s, 70%% D2Q9 64^2..1024^2, "
+                    "30%% D3Q27 64^3..192^3, sessile drops theta 30..150 deg, gamma 0.005..0.03, FP32 / FP16-offset "
+                    "storage, %d..%d steps (full stream / 20)" % (SERVE_N, SERVE_RATE, SERVE_STEPS[0], SERVE_STEPS[1]),
+        "node_updates": total,
+        "batched": {"MLUPS": total / span_s / 1e6, "makespan_s": span_s, "p50_s": _pct(lat_s, 50),
+                    "p99_s": _pct(lat_s, 99), "ok": ok_s, "quantum": SERVE_QUANTUM, "pool_bytes": SERVE_POOL},
+        "plain": {"MLUPS": total / span_p / 1e6, "makespan_s": span_p, "p50_s": _pct(lat_p, 50),
+                  "p99_s": _pct(lat_p, 99), "ok": ok_p},
+        "throughput_ratio": span_p / span_s,
+    }
+
+
 def cpu_baseline(target_s=12.0):
     import numpy as np
     from oracle import oracle as O
@@ -122,6 +212,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=500)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-variants", action="store_true", help="skip the FP64 / FP16-storage runs")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving comparison")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 256 MiB device copy (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -186,6 +277,8 @@ def main():
         "variants": variants,
         "roofline": roof,
     }
+    if not args.no_serving:
+        line["serving"] = serving_leg(L, I)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)

@@ -201,11 +201,14 @@ lbm3_status lbm3_step_batch(lbm3 *const *hs, int32_t n, int64_t nsteps, void *st
 
 /* ------------------------------------------------------------- serving ---
  * Continuous batching: requests (parameters, initial fields, step count)
- * queue on the host; each round retires finished simulations, admits queued
- * ones first-come first-served while their device footprint fits the pool
- * (later, smaller requests may pass one that does not fit, until it has
- * waited max_skips rounds) and enqueues up to `quantum` batched steps of
- * every resident simulation, returning while the GPU works.  Tension
+ * queue on the host.  Resident simulations are split by size into lanes
+ * (below and from 2^18 nodes), each with its own stream, batch tables and
+ * rounds, so small grids are not held to the step time of large ones and the
+ * lanes overlap on the GPU.  A lane's round retires its finished
+ * simulations, admits queued ones of its size first-come first-served while
+ * their device footprint fits the shared pool (later requests may pass one
+ * that does not fit, until it has waited max_skips rounds) and enqueues up
+ * to `quantum` batched steps of everything resident in it.  Tension
  * calibration (lbm3_resolve) runs at submission, on the host. */
 typedef struct lbm3_server lbm3_server;
 
@@ -226,9 +229,11 @@ enum { LBM3_SERVE_FIELDS = 1u };  /* keep the final rho, phi (host copy) */
  * lbm3_footprint plus its share of the batch tables); 0 if invalid. */
 size_t lbm3_server_request_bytes(const lbm3_params *p);
 
-/* pool: device memory, 256-byte aligned, owned by the caller and used only
- * by the server until lbm3_server_destroy; stream: hipStream_t for all of
- * its work; max_resident >= 1 simulations at once; max_skips >= 0. */
+/* pool: device memory (>= 4 MiB), 256-byte aligned, owned by the caller and
+ * used only by the server until lbm3_server_destroy returns; the server's
+ * lane streams (default priority) start after the work enqueued on `stream`
+ * (a hipStream_t) before this call; max_resident >= 1 simulations at once
+ * over all lanes; max_skips >= 0. */
 lbm3_status lbm3_server_create(void *pool, size_t pool_bytes, void *stream, int32_t max_resident,
                                int32_t max_skips, lbm3_server **out);
 
@@ -239,8 +244,9 @@ lbm3_status lbm3_server_create(void *pool, size_t pool_bytes, void *stream, int3
 lbm3_status lbm3_server_submit(lbm3_server *s, const lbm3_params *p, const double *rho0, const double *phi0,
                                int64_t nsteps, uint64_t tag, uint32_t flags);
 
-/* One round (see above).  Blocks only for the previous round's GPU work.
- * n_resident, n_queued (may be NULL): simulations on the device / waiting. */
+/* One round of every lane whose previous round has finished (blocking only
+ * while every lane with work is still busy).  n_resident, n_queued (may be
+ * NULL): simulations on the device / waiting. */
 lbm3_status lbm3_server_run(lbm3_server *s, int64_t quantum, int32_t *n_resident, int32_t *n_queued);
 
 /* Pop the oldest finished result into *out: 1 if one was returned, 0 if none,

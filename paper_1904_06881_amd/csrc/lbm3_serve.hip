@@ -10,6 +10,7 @@
 #include <deque>
 #include <map>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "../../include/lbm3.h"
@@ -100,26 +101,44 @@ size_t table_share(const lbm3_params &p)
     return align256(1024 + 4 * (size_t)blocks);
 }
 
+// Simulations are split by size into lanes, each with its own stream, batch
+// tables and round cadence, so that small grids are not held to the step
+// time of large ones; lanes run concurrently on the GPU.
+const int kLanes = 2;
+const int64_t kSmallNodes = 1 << 18;  // lane 0 below, lane 1 from here on
+
+int lane_of(const lbm3_params &p) { return nodes_of(p) < kSmallNodes ? 0 : 1; }
+
+struct Lane {
+    hipStream_t stream = nullptr;
+    char *image_dev = nullptr;            // batch tables of this lane in the pool
+    unsigned char *image_host = nullptr;  // pinned staging of the tables
+    size_t image_cap = 0, table_used = 0;
+    hipEvent_t round_done = nullptr;
+    bool inflight = false;
+    std::vector<Resident> res;
+};
+
 }  // namespace
 
 struct lbm3_server {
     char *pool = nullptr;
     size_t pool_bytes = 0;
-    hipStream_t stream = nullptr;
     int max_resident = 1, max_skips = 0;
     Arena sims;                // simulation buffers: [0, sim_bytes) of the pool
     size_t sim_bytes = 0;
-    char *image_dev = nullptr; // batch tables: the rest of the pool
-    size_t image_cap = 0, table_used = 0;
-    unsigned char *image_host = nullptr;  // pinned staging of the tables
-    hipEvent_t round_done = nullptr;
-    bool inflight = false;
+    Lane lane[kLanes];
     std::deque<Request> queue;
-    std::vector<Resident> res;
     std::deque<lbm3_result> done;
     std::map<uint64_t, Kept> kept;
     std::chrono::steady_clock::time_point t0;
     double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
+    int resident() const
+    {
+        int n = 0;
+        for (const auto &l : lane) n += (int)l.res.size();
+        return n;
+    }
 };
 
 namespace {
@@ -134,16 +153,21 @@ void fail_result(lbm3_server *s, const Request &r, lbm3_status st)
     s->done.push_back(o);
 }
 
-lbm3_status wait_round(lbm3_server *s)
+// 1: the lane's last round is done (or none is in flight), 0: still running
+int lane_ready(Lane &l, bool block, lbm3_status &st)
 {
-    if (!s->inflight) return LBM3_OK;
-    s->inflight = false;
-    return hipEventSynchronize(s->round_done) == hipSuccess ? LBM3_OK : LBM3_EDEVICE;
+    st = LBM3_OK;
+    if (!l.inflight) return 1;
+    hipError_t e = block ? hipEventSynchronize(l.round_done) : hipEventQuery(l.round_done);
+    if (e == hipErrorNotReady) return 0;
+    l.inflight = false;
+    if (e != hipSuccess) st = LBM3_EDEVICE;
+    return 1;
 }
 
-void retire(lbm3_server *s, size_t i, lbm3_status st)
+void retire(lbm3_server *s, Lane &l, size_t i, lbm3_status st)
 {
-    Resident &r = s->res[i];
+    Resident &r = l.res[i];
     lbm3_result o{};
     o.tag = r.req.tag;
     o.nodes = nodes_of(r.req.p);
@@ -169,19 +193,25 @@ void retire(lbm3_server *s, size_t i, lbm3_status st)
     o.t_done = s->now();
     lbm3_destroy(r.h);
     s->sims.release(r.off, r.req.bytes);
-    s->table_used -= r.req.table;
+    l.table_used -= r.req.table;
     s->done.push_back(o);
-    s->res.erase(s->res.begin() + (long)i);
+    l.res.erase(l.res.begin() + (long)i);
 }
 
-void admit(lbm3_server *s)
+// admit queued requests of lane li in arrival order while they fit
+void admit(lbm3_server *s, int li)
 {
-    for (auto it = s->queue.begin(); it != s->queue.end() && (int)s->res.size() < s->max_resident;) {
+    Lane &l = s->lane[li];
+    for (auto it = s->queue.begin(); it != s->queue.end() && s->resident() < s->max_resident;) {
         Request &r = *it;
+        if (lane_of(r.p) != li) {
+            ++it;
+            continue;
+        }
         size_t off = 0;
-        bool fits = s->table_used + r.table + kTableSlack <= s->image_cap && s->sims.alloc(r.bytes, off);
+        bool fits = l.table_used + r.table + kTableSlack <= l.image_cap && s->sims.alloc(r.bytes, off);
         if (!fits) {
-            // the oldest waiting request holds the line after max_skips rounds
+            // the oldest waiting request holds its lane after max_skips rounds
             if (++r.skips > s->max_skips) break;
             ++it;
             continue;
@@ -191,7 +221,7 @@ void admit(lbm3_server *s)
         m.off = off;
         m.left = m.req.nsteps;
         it = s->queue.erase(it);
-        lbm3_status st = lbm3_create(&m.req.p, s->pool + off, m.req.bytes, s->stream, &m.h);
+        lbm3_status st = lbm3_create(&m.req.p, s->pool + off, m.req.bytes, l.stream, &m.h);
         if (st == LBM3_OK) st = lbm3_init(m.h, m.req.rho0.data(), m.req.phi0.data());
         if (st != LBM3_OK) {
             if (m.h) lbm3_destroy(m.h);
@@ -202,8 +232,47 @@ void admit(lbm3_server *s)
         m.t_admit = s->now();
         m.req.rho0 = std::vector<double>();
         m.req.phi0 = std::vector<double>();
-        s->table_used += m.req.table;
-        s->res.push_back(std::move(m));
+        l.table_used += m.req.table;
+        l.res.push_back(std::move(m));
+    }
+}
+
+// enqueue up to `quantum` batched steps of every resident of the lane
+lbm3_status enqueue_round(Lane &l, int64_t quantum)
+{
+    if (l.res.empty()) return LBM3_OK;
+    // most steps left first: each later segment is a prefix of this order
+    std::stable_sort(l.res.begin(), l.res.end(), [](const Resident &a, const Resident &b) { return a.left > b.left; });
+    std::vector<lbm3 *> hs(l.res.size());
+    for (size_t i = 0; i < hs.size(); ++i) hs[i] = l.res[i].h;
+    lbm3b::Image img;
+    lbm3_status st = lbm3b::build(hs.data(), (int)hs.size(), img);
+    if (st != LBM3_OK) return st;
+    if (img.bytes.size() > l.image_cap) return LBM3_ENOMEM;
+    std::memcpy(l.image_host, img.bytes.data(), img.bytes.size());
+    if (hipMemcpyAsync(l.image_dev, l.image_host, img.bytes.size(), hipMemcpyHostToDevice, l.stream) != hipSuccess)
+        return LBM3_EDEVICE;
+    int64_t prev = 0;
+    for (size_t k = hs.size(); k-- > 0;) {
+        int64_t a = std::min<int64_t>(quantum, l.res[k].left);
+        if (a > prev) {
+            st = lbm3b::enqueue(hs.data(), (int)k + 1, img, l.image_dev, prev, a - prev, l.stream);
+            if (st != LBM3_OK) return st;
+            prev = a;
+        }
+    }
+    for (auto &r : l.res) r.left -= std::min<int64_t>(quantum, r.left);
+    if (hipEventRecord(l.round_done, l.stream) != hipSuccess) return LBM3_EDEVICE;
+    l.inflight = true;
+    return LBM3_OK;
+}
+
+void release_lanes(lbm3_server *s)
+{
+    for (auto &l : s->lane) {
+        if (l.image_host) (void)hipHostFree(l.image_host);
+        if (l.round_done) (void)hipEventDestroy(l.round_done);
+        if (l.stream) (void)hipStreamDestroy(l.stream);
     }
 }
 
@@ -222,23 +291,34 @@ lbm3_status lbm3_server_create(void *pool, size_t pool_bytes, void *stream, int3
 {
     if (!out) return LBM3_EINVAL;
     *out = nullptr;
-    if (!pool || ((uintptr_t)pool & 255) != 0 || pool_bytes < (1u << 20) || max_resident < 1 || max_skips < 0)
+    if (!pool || ((uintptr_t)pool & 255) != 0 || pool_bytes < (4u << 20) || max_resident < 1 || max_skips < 0)
         return LBM3_EINVAL;
     lbm3_server *s = new (std::nothrow) lbm3_server();
     if (!s) return LBM3_ENOMEM;
     s->pool = (char *)pool;
     s->pool_bytes = pool_bytes;
-    s->stream = (hipStream_t)stream;
     s->max_resident = max_resident;
     s->max_skips = max_skips;
-    // tables: 1/256 of the pool (at least 1 MiB) at its end
-    s->image_cap = align256(std::max<size_t>(1u << 20, pool_bytes / 256));
-    s->sim_bytes = (pool_bytes - s->image_cap) & ~(size_t)255;
-    s->image_dev = s->pool + s->sim_bytes;
+    // tables: 1/256 of the pool (at least 1 MiB) per lane at its end
+    size_t cap = align256(std::max<size_t>(1u << 20, pool_bytes / 256));
+    s->sim_bytes = (pool_bytes - kLanes * cap) & ~(size_t)255;
     s->sims.reset(s->sim_bytes);
-    if (hipHostMalloc((void **)&s->image_host, s->image_cap, hipHostMallocDefault) != hipSuccess ||
-        hipEventCreateWithFlags(&s->round_done, hipEventDisableTiming) != hipSuccess) {
-        if (s->image_host) (void)hipHostFree(s->image_host);
+    // lane streams start after the work already on the caller's stream
+    hipEvent_t ready = nullptr;
+    bool ok = hipEventCreateWithFlags(&ready, hipEventDisableTiming) == hipSuccess &&
+              hipEventRecord(ready, (hipStream_t)stream) == hipSuccess;
+    for (int i = 0; i < kLanes && ok; ++i) {
+        Lane &l = s->lane[i];
+        l.image_cap = cap;
+        l.image_dev = s->pool + s->sim_bytes + (size_t)i * cap;
+        ok = hipStreamCreateWithFlags(&l.stream, hipStreamNonBlocking) == hipSuccess &&
+             hipHostMalloc((void **)&l.image_host, cap, hipHostMallocDefault) == hipSuccess &&
+             hipEventCreateWithFlags(&l.round_done, hipEventDisableTiming) == hipSuccess &&
+             hipStreamWaitEvent(l.stream, ready, 0) == hipSuccess;
+    }
+    if (ready) (void)hipEventDestroy(ready);
+    if (!ok) {
+        release_lanes(s);
         delete s;
         return LBM3_EDEVICE;
     }
@@ -271,7 +351,7 @@ lbm3_status lbm3_server_submit(lbm3_server *s, const lbm3_params *p, const doubl
     }
     r.bytes = align256(lbm3_footprint(&r.p));
     r.table = table_share(r.p);
-    if (r.bytes > s->sim_bytes || r.table + kTableSlack > s->image_cap) {
+    if (r.bytes > s->sim_bytes || r.table + kTableSlack > s->lane[lane_of(r.p)].image_cap) {
         fail_result(s, r, LBM3_ENOMEM);
         return LBM3_OK;
     }
@@ -285,39 +365,29 @@ lbm3_status lbm3_server_submit(lbm3_server *s, const lbm3_params *p, const doubl
 lbm3_status lbm3_server_run(lbm3_server *s, int64_t quantum, int32_t *n_resident, int32_t *n_queued)
 {
     if (!s || quantum < 1) return LBM3_EINVAL;
-    lbm3_status st = wait_round(s);
-    if (st != LBM3_OK) return st;
-    for (size_t i = s->res.size(); i-- > 0;)
-        if (s->res[i].left == 0) retire(s, i, LBM3_OK);
-    admit(s);
-    if (!s->res.empty()) {
-        // most steps left first: each later segment is a prefix of this order
-        std::stable_sort(s->res.begin(), s->res.end(),
-                         [](const Resident &a, const Resident &b) { return a.left > b.left; });
-        std::vector<lbm3 *> hs(s->res.size());
-        for (size_t i = 0; i < hs.size(); ++i) hs[i] = s->res[i].h;
-        lbm3b::Image img;
-        st = lbm3b::build(hs.data(), (int)hs.size(), img);
-        if (st != LBM3_OK) return st;
-        if (img.bytes.size() > s->image_cap) return LBM3_ENOMEM;
-        std::memcpy(s->image_host, img.bytes.data(), img.bytes.size());
-        if (hipMemcpyAsync(s->image_dev, s->image_host, img.bytes.size(), hipMemcpyHostToDevice, s->stream) !=
-            hipSuccess)
-            return LBM3_EDEVICE;
-        int64_t prev = 0;
-        for (size_t k = hs.size(); k-- > 0;) {
-            int64_t a = std::min<int64_t>(quantum, s->res[k].left);
-            if (a > prev) {
-                st = lbm3b::enqueue(hs.data(), (int)k + 1, img, s->image_dev, prev, a - prev, s->stream);
-                if (st != LBM3_OK) return st;
-                prev = a;
+    // serve every lane whose last round is done; return once a lane has
+    // enqueued work or produced results, or when nothing is on the GPU
+    for (;;) {
+        bool busy = false, acted = false;
+        for (int i = 0; i < kLanes; ++i) {
+            Lane &l = s->lane[i];
+            lbm3_status st;
+            if (!lane_ready(l, false, st)) {
+                busy = true;
+                continue;
             }
+            if (st != LBM3_OK) return st;
+            const size_t results = s->done.size();
+            for (size_t k = l.res.size(); k-- > 0;)
+                if (l.res[k].left == 0) retire(s, l, k, LBM3_OK);
+            admit(s, i);
+            if ((st = enqueue_round(l, quantum)) != LBM3_OK) return st;
+            acted = acted || l.inflight || s->done.size() != results;
         }
-        for (auto &r : s->res) r.left -= std::min<int64_t>(quantum, r.left);
-        if (hipEventRecord(s->round_done, s->stream) != hipSuccess) return LBM3_EDEVICE;
-        s->inflight = true;
+        if (acted || !busy) break;
+        std::this_thread::sleep_for(std::chrono::microseconds(20));
     }
-    if (n_resident) *n_resident = (int32_t)s->res.size();
+    if (n_resident) *n_resident = (int32_t)s->resident();
     if (n_queued) *n_queued = (int32_t)s->queue.size();
     return LBM3_OK;
 }
@@ -347,10 +417,14 @@ double lbm3_server_clock(const lbm3_server *s) { return s ? s->now() : 0.0; }
 lbm3_status lbm3_server_destroy(lbm3_server *s)
 {
     if (!s) return LBM3_EINVAL;
-    lbm3_status st = wait_round(s);
-    for (auto &r : s->res) lbm3_destroy(r.h);
-    if (s->image_host) (void)hipHostFree(s->image_host);
-    if (s->round_done) (void)hipEventDestroy(s->round_done);
+    lbm3_status st = LBM3_OK;
+    for (auto &l : s->lane) {
+        lbm3_status q;
+        lane_ready(l, true, q);
+        if (q != LBM3_OK) st = q;
+        for (auto &r : l.res) lbm3_destroy(r.h);
+    }
+    release_lanes(s);
     delete s;
     return st;
 }
