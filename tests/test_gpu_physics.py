@@ -1,0 +1,139 @@
+"""Physics the paper fixes, on the GPU path in FP64 (the path is parity-pinned
+to the oracle, so these also check the oracle's readings at sizes the oracle
+would need minutes for).
+
+Passing: the liquid-liquid (2-3) interface relaxes to the tanh profile of
+width alpha_23 = W/4 (Sec. III), and a 2-3 drop obeys the Laplace law with
+the closed-form tension gamma_23 = alpha (lambda_2 + lambda_3)/6 (Eq. 38).
+
+Expected failures, kept to track them: with the readings of the force and
+wall discretisation in use, curved liquid-gas interfaces carry an excess
+tension (Laplace gamma_12 about 1.5-1.8x the calibrated one, gas density
+above coexistence), sessile liquid-gas drops end near 90 degrees whatever
+theta_21 is, and liquid-liquid drops drift away from theta_23 over tens of
+thousands of steps, while the paper reports angles within 1 degree in
+[60, 120] degrees (Sec. IV C).
+"""
+import sys
+
+import numpy as np
+import pytest
+from scipy.optimize import curve_fit
+
+from oracle import oracle as O
+from paper_1904_06881_amd import inputs as I
+from paper_1904_06881_amd import lbm3 as L
+
+pytestmark = pytest.mark.gpu
+
+G = (0.01, 0.01, 0.01)
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def oracle_params(sim, n, walls=True, theta=90.0):
+    d = sim.derived
+    eos = {k: getattr(d, k) for k in ("a", "b", "T", "C", "psi0", "rho_l", "rho_g")}
+    return O.make_params(2, n, lam=list(d.lam), kap=list(d.kap), eos=eos, rho_l=d.rho_l, rho_g=d.rho_g,
+                         walls=walls, theta_deg=theta)
+
+
+def bulk_pressure(po, rho, phi):
+    return O.local_thermo(po, rho, phi, [0, 0], [0, 0], 0.0, 0.0)[2][0, 0]
+
+
+def test_u5_flat_liquid_liquid_interface_is_tanh():
+    """Sec. III: C2 across a flat 2-3 interface is (1 + tanh(x / 2 alpha))/2
+    with alpha = W/4 = 1; fitted alpha within 2 %."""
+    p = L.make_params(L.D2Q9, (128, 4), gamma=G, width=4.0, walls=False, precision=L.FP64)
+    s = L.Sim(p)
+    s.init(*I.flat_interface_2d(128, 4, left=(0, 1), right=(1, 0)))
+    s.step(4000)
+    r, ph = s.fields()
+    po = oracle_params(s, (128, 4), walls=False)
+    s.close()
+    C1, C2, C3 = O.concentrations(po, r, ph)
+    x = np.arange(64.0)
+    f = lambda x, x0, a: 0.5 * (1.0 + np.tanh((x - x0) / (2.0 * a)))
+    (x0, a), _ = curve_fit(f, x, C2[1, :64], p0=(32.0, 1.0))
+    say("alpha", a, "x0", x0)
+    assert abs(a - 1.0) < 0.02
+    assert abs(x0 - 32.0) < 0.05
+
+
+def laplace(kind, R, steps):
+    nb = 4 * R + 32
+    p = L.make_params(L.D2Q9, (nb, nb), gamma=G, width=4.0, walls=False, precision=L.FP64)
+    s = L.Sim(p)
+    outside = (0, 1) if kind == "LL" else (0, 0)
+    s.init(*I.bubble_2d(nb, nb, R, inside=(1, 0), outside=outside))
+    s.step(steps)
+    r, ph = s.fields()
+    po = oracle_params(s, (nb, nb), walls=False)
+    lam = s.derived.lam
+    s.close()
+    c = nb // 2
+    dP = bulk_pressure(po, r[c, c], ph[c, c]) - bulk_pressure(po, r[2, 2], ph[2, 2])
+    C1, C2, C3 = O.concentrations(po, r, ph)
+    xs, ys = O.contour_points_2d(C2)
+    Rf = O.kasa_fit(np.asarray(xs), np.asarray(ys))[2]
+    return dP * Rf, (lam[1] + lam[2]) / 6.0, r[2, 2]
+
+
+def test_u6_laplace_liquid_liquid():
+    """A 2-3 drop: dP R the same for R = 16 and 32 within 3 %, and within 5 %
+    of the closed-form gamma_23 = alpha (lambda_2 + lambda_3)/6 (Eq. 38)."""
+    g16, closed, _ = laplace("LL", 16, 20000)
+    g32, _, _ = laplace("LL", 32, 20000)
+    say("dP R", g16, g32, "closed form", closed)
+    assert abs(g16 - g32) < 0.03 * closed
+    assert abs(g16 - closed) < 0.05 * closed and abs(g32 - closed) < 0.05 * closed
+
+
+@pytest.mark.xfail(reason="curved liquid-gas interfaces carry an excess tension with the link-pressure "
+                          "ideal force (dP R about 0.017-0.018 for gamma_12 = 0.01)", strict=False)
+def test_u6_laplace_liquid_gas():
+    g16, _, gas16 = laplace("LG", 16, 20000)
+    g32, _, gas32 = laplace("LG", 32, 20000)
+    say("dP R", g16, g32, "gas density", gas16, gas32)
+    assert abs(g16 - 0.01) < 0.05 * 0.01 and abs(g32 - 0.01) < 0.05 * 0.01
+
+
+def sessile_angle(theta, liquid_liquid, steps):
+    nx, ny, R = 240, 100, 30.0
+    th = (90.0, 90.0, theta) if liquid_liquid else theta
+    p = L.make_params(L.D2Q9, (nx, ny), gamma=G, width=4.0, theta_deg=th, precision=L.FP64)
+    s = L.Sim(p)
+    if liquid_liquid:
+        x, y = np.mgrid[0:ny, 0:nx][1].astype(float), np.mgrid[0:ny, 0:nx][0].astype(float)
+        yc = 0.5 - R * np.cos(np.radians(theta))
+        sh = I.profile(R - np.sqrt((x - nx / 2) ** 2 + (y - yc) ** 2), 4.0)
+        s.init(*I.fields_from_conc(sh, 1.0 - sh))
+    else:
+        s.init(*I.cap_drop_2d(nx, ny, R, theta))
+    s.step(steps)
+    r, ph = s.fields()
+    po = oracle_params(s, (nx, ny), theta=th)
+    s.close()
+    C1, C2, C3 = O.concentrations(po, r, ph)
+    return O.contact_angle_2d(C2, exclude=8.0)[0]
+
+
+@pytest.mark.xfail(reason="2-3 drops drift from theta_23 over tens of thousands of steps "
+                          "(theta 90 -> 84, 120 -> 110 degrees after 40k steps)", strict=False)
+@pytest.mark.parametrize("theta", [60.0, 120.0])
+def test_u8_contact_angle_liquid_liquid(theta):
+    a = sessile_angle(theta, True, 30000)
+    say("theta_23", theta, "measured", a)
+    assert abs(a - theta) < 1.0
+
+
+@pytest.mark.xfail(reason="liquid-gas drops end near 90 degrees whatever theta_21 is", strict=False)
+@pytest.mark.parametrize("theta", [60.0, 120.0])
+def test_u8_contact_angle_liquid_gas(theta):
+    a = sessile_angle(theta, False, 16000)
+    say("theta_21", theta, "measured", a)
+    assert abs(a - theta) < 1.0
