@@ -106,6 +106,14 @@ template <typename R> struct Thermo {
 
 template <typename R> __device__ __forceinline__ R gfun(R x) { return x * (x - (R)0.5) * (x - (R)1); }
 
+// a / b: correctly rounded in FP64; in FP32 a times the hardware reciprocal
+// (about 1 ulp), well inside the FP32 path's error budget
+template <typename R> __device__ __forceinline__ R fdiv(R a, R b) { return a / b; }
+template <> __device__ __forceinline__ float fdiv<float>(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+// sqrt: correctly rounded in FP64, the hardware square root in FP32
+template <typename R> __device__ __forceinline__ R fsqrt(R v) { return sqrt(v); }
+template <> __device__ __forceinline__ float fsqrt<float>(float v) { return __builtin_amdgcn_sqrtf(v); }
+
 // Bulk chemical potentials and free energy (Eqs. 2, 4-7, 11-12, 15): C1 from
 // rho, C2/C3 from rho and phi; dPsi and Psi of the Carnahan-Starling EOS; the
 // rho derivative of the lambda2/lambda3 wells is +(lambda2 g(C2) +
@@ -156,9 +164,16 @@ __device__ __forceinline__ void thermo(const Thermo<R> &t, R rho, R phi, const R
         }
 }
 
-// Link pressure of the ideal part of the force: equals rho/3 for equal
-// densities; its lattice divergence keeps an exponential density profile an
-// exact steady state of the product-form ELBM.
+// Link pressure of the ideal part of the force,
+// 2 rho_x rho_y / (rho_x + rho_y + 4 sqrt(rho_x rho_y)), from qx = sqrt(rho_x)
+// and qy = sqrt(rho_y): equals rho/3 for equal densities; its lattice
+// divergence keeps an exponential density profile an exact steady state of
+// the product-form ELBM.
+template <typename R> __device__ __forceinline__ R link_q(R qx, R qy)
+{
+    const R m = qx * qy, s = qx + qy;
+    return fdiv((R)2 * m * m, s * s + (R)2 * m);
+}
 template <typename R> __device__ __forceinline__ R link_p(R rx, R ry)
 {
     return (R)2 * rx * ry / (rx + ry + (R)4 * sqrt(rx * ry));
@@ -172,8 +187,8 @@ __device__ __forceinline__ void feq_factors(R u, R *fac)
 {
     R s = sqrt((R)1 + (R)3 * u * u);
     R A = (R)2 - s;
-    R B = ((R)2 * u + s) / ((R)1 - u);
-    fac[0] = (R)(1.0 / 6.0) * A / B;
+    R B = fdiv((R)2 * u + s, (R)1 - u);
+    fac[0] = fdiv((R)(1.0 / 6.0) * A, B);
     fac[1] = (R)(2.0 / 3.0) * A;
     fac[2] = (R)(1.0 / 6.0) * A * B;
 }
@@ -215,19 +230,21 @@ __device__ __forceinline__ R entropic_alpha(const R *fp, R *dx, R eps, R tol, in
     for (int i = 0; i < Q; ++i) pos = pos && (fp[i] > (R)0);
     if (!pos) { kind = 2; is_x = false; return (R)2; }
     is_x = true;
-    R xmax = 0, amax = (R)INFINITY;
+    R xmax = 0, xmin = 0;
     R S2 = 0, S3 = 0, S4 = 0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const R x = dx[i] / fp[i];
+        const R x = fdiv(dx[i], fp[i]);
         dx[i] = x;
         xmax = fmax(xmax, fabs(x));
-        if (x < (R)0) amax = fmin(amax, (R)-1 / x);
+        xmin = fmin(xmin, x);
         const R x2 = x * x;
         S2 += fp[i] * x2;
         S3 += fp[i] * x2 * x;
         S4 += fp[i] * x2 * x2;
     }
+    // min over x < 0 of -1/x is -1/min(x) (the division is monotone)
+    const R amax = xmin < (R)0 ? (R)-1 / xmin : (R)INFINITY;
     const R den = (R)3 * S2 - (R)4 * S3;
     const R as = den > (R)0 ? (R)2 + (S3 - (R)2 * S4) / den : (R)2;
     if (xmax < eps) { kind = 0; return as; }
@@ -511,6 +528,11 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
     constexpr int NIP = D == 3 ? 9 : 3;          // in-plane neighbour offsets
     __shared__ R s_r[5][FS];
     __shared__ R s_p[5][FS];
+    // QR: keep sqrt(rho) in a ring for the link pressures (one square root
+    // per field element instead of one per link); the small 2D tile, whose
+    // run time is the latency of its plane stages, takes it per link
+    constexpr bool QR = !(D == 2 && NTH <= 64);
+    __shared__ R s_q[5][QR ? FS : 1];
     __shared__ R s_t[3][NP + 1][TS];
     __shared__ int s_cnt[3];
 
@@ -564,7 +586,9 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
         for (int m = 0; m < NLD; ++m) {
             int k = tid + m * NTH;
             if (NLD * NTH == FS || k < FS) {
-                s_r[slot][k] = rho[base + ld_idx[m]];
+                const R r = rho[base + ld_idx[m]];
+                s_r[slot][k] = r;
+                if constexpr (QR) s_q[slot][k] = fsqrt(r);
                 s_p[slot][k] = phi[base + ld_idx[m]];
             }
         }
@@ -600,6 +624,7 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
             R gr_, gp_;
             ghost_value<D, R>(kp, wall, get, gr_, gp_);
             s_r[sg][k] = gr_;
+            if constexpr (QR) s_q[sg][k] = fsqrt(gr_);
             s_p[sg][k] = gp_;
             if (own & (1u << m)) {
                 rho[bg + ld_idx[m]] = gr_;
@@ -699,7 +724,7 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
         if (active) {
             const int sm = (p + 9) % 5, s0 = (p + 10) % 5, sp = (p + 11) % 5;
             const int tm = (p + 9) % 3, t0 = (p + 10) % 3, tp = (p + 11) % 3;
-            const R r0 = s_r[s0][fcen], p0 = s_p[s0][fcen];
+            const R r0 = s_r[s0][fcen], p0 = s_p[s0][fcen], q0 = QR ? s_q[s0][fcen] : (R)0;
             const bool first = walls && (p == 1 || p == nw - 2);
             R F[3] = {0, 0, 0};
             if (first) {
@@ -710,7 +735,10 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
 #pragma unroll
                     for (int a = 0; a < D; ++a)
                         F[a] += (R)0.5 * (s_t[t0][sym(D, a, b)][tcen + ot] - s_t[t0][sym(D, a, b)][tcen - ot]);
-                    F[b] += link_p(r0, s_r[s0][fcen + of]) - link_p(r0, s_r[s0][fcen - of]);
+                    if constexpr (QR)
+                        F[b] += link_q(q0, s_q[s0][fcen + of]) - link_q(q0, s_q[s0][fcen - of]);
+                    else
+                        F[b] += link_p(r0, s_r[s0][fcen + of]) - link_p(r0, s_r[s0][fcen - of]);
                 }
             } else {
 #pragma unroll
@@ -722,7 +750,7 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
                     const int slt = cw < 0 ? tm : (cw > 0 ? tp : t0);
                     const int slf = cw < 0 ? sm : (cw > 0 ? sp : s0);
                     const R w3 = (R)(3.0 * wgt(D, i)), w6 = (R)(6.0 * wgt(D, i));
-                    const R pl = link_p(r0, s_r[slf][fcen + offf]);
+                    const R pl = QR ? link_q(q0, s_q[slf][fcen + offf]) : link_p(r0, s_r[slf][fcen + offf]);
 #pragma unroll
                     for (int a = 0; a < D; ++a) {
                         R acc = 0;
