@@ -576,22 +576,42 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
     // step); 3D: they come filled from the ghost-layer kernel
     constexpr bool GK = D == 2;
 
-    // plane q of rho, phi into the LDS ring (ghost layers: ghost_plane)
-    auto load_fields = [&](int q) {
-        if (walls && (q < 0 || q > nw - 1)) return;
-        if (GK && walls && (q == 0 || q == nw - 1)) return;
-        const int slot = (q + 10) % 5;
+    // plane q of rho, phi into the LDS ring (ghost layers: ghost_plane), in
+    // two halves: fetch issues the loads into registers, commit stores them,
+    // so a plane's loads can be in flight while the previous one is worked on
+    auto has_fields = [&](int q) {
+        if (walls && (q < 0 || q > nw - 1)) return false;
+        return !(GK && walls && (q == 0 || q == nw - 1));
+    };
+    R pre_r[NLD], pre_p[NLD];
+    auto fetch = [&](int q) {
+        if (!has_fields(q)) return;
         const unsigned base = (unsigned)plane(q) * PS;
 #pragma unroll
         for (int m = 0; m < NLD; ++m) {
             int k = tid + m * NTH;
             if (NLD * NTH == FS || k < FS) {
-                const R r = rho[base + ld_idx[m]];
-                s_r[slot][k] = r;
-                if constexpr (QR) s_q[slot][k] = fsqrt(r);
-                s_p[slot][k] = phi[base + ld_idx[m]];
+                pre_r[m] = rho[base + ld_idx[m]];
+                pre_p[m] = phi[base + ld_idx[m]];
             }
         }
+    };
+    auto commit = [&](int q) {
+        if (!has_fields(q)) return;
+        const int slot = (q + 10) % 5;
+#pragma unroll
+        for (int m = 0; m < NLD; ++m) {
+            int k = tid + m * NTH;
+            if (NLD * NTH == FS || k < FS) {
+                s_r[slot][k] = pre_r[m];
+                if constexpr (QR) s_q[slot][k] = fsqrt(pre_r[m]);
+                s_p[slot][k] = pre_p[m];
+            }
+        }
+    };
+    auto load_fields = [&](int q) {
+        fetch(q);
+        commit(q);
     };
 
     // Wall ghost layer q (0 or nw - 1) over the tile and a halo of 2 (Sec. IV)
@@ -668,8 +688,9 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
         }
     };
 
-    // prologue: fields pb-2 .. pb+1, -P planes pb-1 .. pb
+    // prologue: fields pb-2 .. pb+1, -P planes pb-1 .. pb; plane pb+2 fetched
     for (int q = pb - 2; q <= pb + 1; ++q) load_fields(q);
+    fetch(pb + 2);
     __syncthreads();
     if (GK && walls && (pb - 2 <= 0 || pb + 1 >= nw - 1)) {
         for (int q = pb - 2; q <= pb + 1; ++q)
@@ -717,7 +738,8 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
                 }
             }
         }
-        load_fields(p + 2);
+        commit(p + 2);
+        if (p + 1 < pe) fetch(p + 3);
         __syncthreads();
         compute_T(p + 1);
         __syncthreads();
