@@ -50,7 +50,7 @@ struct SimDesc {
 };
 
 // Fused launch geometry of one simulation: tile class (0: 2D 62-node tiles,
-// 1: 2D 254-node tiles, 2: 3D 32x8 tiles (32x4 in FP64)), in-plane tiles,
+// 1: 2D 254-node tiles, 2: 3D 32x16 tiles (32x4 in FP64)), in-plane tiles,
 // planes per block and blocks along the wall axis.
 struct FusedGeom {
     int cls, ntiles, chunk, nchunks;

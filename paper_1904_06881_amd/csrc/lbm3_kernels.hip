@@ -1255,7 +1255,7 @@ static void tile_of_class(int cls, int prec, int &TX, int &TY)
 {
     if (cls == 0) { TX = 62; TY = 1; }
     else if (cls == 1) { TX = 254; TY = 1; }
-    else { TX = 32; TY = prec == P64 ? 4 : 8; }
+    else { TX = 32; TY = prec == P64 ? 4 : 16; }
 }
 
 static int fused_class(const KParams &kp)
@@ -1307,8 +1307,8 @@ int launch_fused(const KParams &kp, int prec, const Buffers &b, int pc, int fc, 
         return fused_t<2, P16, 254, 1, 256>(kp, b, pc, fc, st);
     }
     if (prec == P64) return fused_t<3, P64, 32, 4, 128>(kp, b, pc, fc, st);
-    if (prec == P32) return fused_t<3, P32, 32, 8, 256>(kp, b, pc, fc, st);
-    return fused_t<3, P16, 32, 8, 256>(kp, b, pc, fc, st);
+    if (prec == P32) return fused_t<3, P32, 32, 16, 512>(kp, b, pc, fc, st);
+    return fused_t<3, P16, 32, 16, 512>(kp, b, pc, fc, st);
 }
 
 // ------------------------------------------------------- batched launches
@@ -1375,8 +1375,8 @@ int launch_fused_batch(int cls, int prec, const SimDesc *d, const int *sim, long
         else k_fused_batch<2, P16, 254, 1, 256><<<grid, 256, 0, st>>>(d, sim, phase);
     } else {
         if (prec == P64) k_fused_batch<3, P64, 32, 4, 128><<<grid, 128, 0, st>>>(d, sim, phase);
-        else if (prec == P32) k_fused_batch<3, P32, 32, 8, 256><<<grid, 256, 0, st>>>(d, sim, phase);
-        else k_fused_batch<3, P16, 32, 8, 256><<<grid, 256, 0, st>>>(d, sim, phase);
+        else if (prec == P32) k_fused_batch<3, P32, 32, 16, 512><<<grid, 512, 0, st>>>(d, sim, phase);
+        else k_fused_batch<3, P16, 32, 16, 512><<<grid, 512, 0, st>>>(d, sim, phase);
     }
     return LBM3_CHECK_LAUNCH();
 }
