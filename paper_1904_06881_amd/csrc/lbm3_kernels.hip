@@ -110,6 +110,22 @@ template <typename R> __device__ __forceinline__ R gfun(R x) { return x * (x - (
 // (about 1 ulp), well inside the FP32 path's error budget
 template <typename R> __device__ __forceinline__ R fdiv(R a, R b) { return a / b; }
 template <> __device__ __forceinline__ float fdiv<float>(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+// log1p: the library's in FP64; in FP32, for |y| < 0.28 the atanh series
+// 2 (s + s^3/3 + ... + s^9/9), s = y/(2 + y) (|s| < 0.14, truncation < 1e-9
+// relative), else the hardware log2 of 1 + y; about 3 ulp at worst
+template <typename R> __device__ __forceinline__ R flog1p(R y) { return log1p(y); }
+template <> __device__ __forceinline__ float flog1p<float>(float y)
+{
+    const float s = y * __builtin_amdgcn_rcpf(2.0f + y), s2 = s * s;
+    float p = 1.0f / 9.0f;
+    p = p * s2 + 1.0f / 7.0f;
+    p = p * s2 + 1.0f / 5.0f;
+    p = p * s2 + 1.0f / 3.0f;
+    p = p * s2 + 1.0f;
+    const float series = 2.0f * s * p;
+    const float direct = __builtin_amdgcn_logf(1.0f + y) * 0.69314718055994531f;
+    return fabsf(y) < 0.28f ? series : direct;
+}
 // sqrt: correctly rounded in FP64, the hardware square root in FP32
 template <typename R> __device__ __forceinline__ R fsqrt(R v) { return sqrt(v); }
 template <> __device__ __forceinline__ float fsqrt<float>(float v) { return __builtin_amdgcn_sqrtf(v); }
@@ -250,7 +266,7 @@ __device__ __forceinline__ R entropic_alpha(const R *fp, R *dx, R eps, R tol, in
     if (xmax < eps) { kind = 0; return as; }
     R K = 0;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) K += fp[i] * dx[i] * log1p(dx[i]);
+    for (int i = 0; i < Q; ++i) K += fp[i] * dx[i] * flog1p(dx[i]);
     R al;
     if (den > (R)0 && as > (R)1 && as < amax) al = as;
     else al = ((R)2 < amax) ? (R)2 : (R)0.5 * ((R)1 + amax);
@@ -261,7 +277,7 @@ __device__ __forceinline__ R entropic_alpha(const R *fp, R *dx, R eps, R tol, in
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             const R ax = al * dx[i];
-            const R la = log1p(ax);
+            const R la = flog1p(ax);
             G += fp[i] * (((R)1 + ax) * la - ax);
             G1 += fp[i] * dx[i] * la;
         }
