@@ -126,6 +126,9 @@ template <> __device__ __forceinline__ float flog1p<float>(float y)
     const float direct = __builtin_amdgcn_logf(1.0f + y) * 0.69314718055994531f;
     return fabsf(y) < 0.28f ? series : direct;
 }
+// log: the library's in FP64, the hardware log2 times ln 2 in FP32
+template <typename R> __device__ __forceinline__ R flog(R v) { return log(v); }
+template <> __device__ __forceinline__ float flog<float>(float v) { return __builtin_amdgcn_logf(v) * 0.69314718055994531f; }
 // sqrt: correctly rounded in FP64, the hardware square root in FP32
 template <typename R> __device__ __forceinline__ R fsqrt(R v) { return sqrt(v); }
 template <> __device__ __forceinline__ float fsqrt<float>(float v) { return __builtin_amdgcn_sqrtf(v); }
@@ -144,7 +147,7 @@ __device__ __forceinline__ void bulk(const Thermo<R> &t, R rho, R phi, R &mrb, R
     R br = t.b * rho;
     R d = br - (R)4;
     R id = (R)1 / d;
-    R lr = log(rho);
+    R lr = flog(rho);
     R dpsi = t.C - (R)2 * t.a * rho + t.T * ((R)1 + lr) + (R)16 * t.T * (br - (R)12) * id * id * id;
     R psi = rho * (t.C - t.a * rho - (R)8 * t.T * (br - (R)6) * id * id + t.T * lr);
     R g2 = gfun(C2), g3 = gfun(C3);
@@ -201,7 +204,7 @@ template <typename R> __device__ __forceinline__ R link_p(R rx, R ry)
 template <typename R>
 __device__ __forceinline__ void feq_factors(R u, R *fac)
 {
-    R s = sqrt((R)1 + (R)3 * u * u);
+    R s = fsqrt((R)1 + (R)3 * u * u);
     R A = (R)2 - s;
     R B = fdiv((R)2 * u + s, (R)1 - u);
     fac[0] = fdiv((R)(1.0 / 6.0) * A, B);
