@@ -9,7 +9,8 @@ synthetic (seeded geometry) and resident in HBM before the timed region.
 
 Prints one JSON line: MLUPS over fluid nodes, the roofline of the dominant
 kernel from HIP events on the library's stream, and the CPU oracle's MLUPS on
-a bounded sample of the same workload.
+a bounded sample of the same workload; beside them the HBM fractions of the
+256^3 D3Q27 and 4096 x 256 D2Q9 grids, and the serving comparison.
 """
 import argparse
 import json
@@ -90,6 +91,58 @@ def run_gpu(L, I, precision, steps, warmup):
     obs = sim.observe()
     sim.close()
     return wall, prof, obs
+
+
+# Large grids: the other two stencil workloads at full size, timed with the
+# same sampled events (fused-launch HBM fraction at algorithmic bytes).
+#   D3Q27 lubricated sessile drop, 256^3, sphere r = 48 on an 8-node film,
+#   gamma (0.02, 0.02, 0.01), 90 deg walls: FP32 and FP16-offset storage;
+#   D2Q9 drop train, 4096 x 256, 16 alternating drops r = 40 spaced 200,
+#   theta (45, 120, 90) deg: FP32.
+LARGE = (
+    ("d3q27_256cube_fp32", "D3Q27", (256, 256, 256), "fp32", 20, 5),
+    ("d3q27_256cube_fp16s", "D3Q27", (256, 256, 256), "fp16s", 20, 5),
+    ("d2q9_4096x256_fp32", "D2Q9", (4096, 256), "fp32", 400, 100),
+)
+
+
+def large_grids(L, I):
+    import torch
+    out = {}
+    init3 = None
+    for name, lat, n, prec, steps, warm in LARGE:
+        P = {"fp32": L.FP32, "fp16s": L.FP16S}[prec]
+        if lat == "D3Q27":
+            p = L.make_params(L.D3Q27, n, gamma=(0.02, 0.02, 0.01), width=4.0, theta_deg=90.0, precision=P)
+            if init3 is None:
+                init3 = I.lubricated_drop_3d(*n, 48, film=8)
+            init, Q, fluid = init3, 27, n[0] * n[1] * (n[2] - 2)
+        else:
+            p = L.make_params(L.D2Q9, n, gamma=(0.01, 0.01, 0.01), width=4.0, theta_deg=(45.0, 120.0, 90.0),
+                              precision=P)
+            init, Q, fluid = I.drop_train_2d(*n), 9, n[0] * (n[1] - 2)
+        s = L.Sim(p, device="cuda:0")
+        s.init(*init)
+        s.step(warm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pr = s.step_profiled(steps, 5)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        o = s.observe()
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+        fb, mb, ab = bytes_per_node(Q, 2 if prec == "fp16s" else 4, 4, prec == "fp16s")
+        fgbs = fb * fluid / (pr["fused"] * 1e-3) / 1e9
+        mgbs = mb * fluid / (pr["moments"] * 1e-3) / 1e9
+        out[name] = {"MLUPS": fluid * steps / wall / 1e6, "ms_per_step": 1e3 * wall / steps,
+                     "fused_ms": pr["fused"], "fused_GBs": fgbs, "fused_frac": fgbs / HBM_PEAK_GBS,
+                     "moments_ms": pr["moments"], "moments_GBs": mgbs, "moments_frac": mgbs / HBM_PEAK_GBS,
+                     "bytes_per_node": {"fused": fb, "moments": mb, "step_min": ab},
+                     "step_frac": fluid * steps / wall * ab / (HBM_PEAK_GBS * 1e9),
+                     "n_bad": o["n_bad"]}
+    return out
 
 
 # Serving sample: 48 requests of the serving stream (Poisson arrivals at 16
@@ -213,6 +266,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-variants", action="store_true", help="skip the FP64 / FP16-storage runs")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving comparison")
+    ap.add_argument("--no-large", action="store_true", help="skip the 256^3 and 4096x256 grids")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 256 MiB device copy (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -277,6 +331,8 @@ def main():
         "variants": variants,
         "roofline": roof,
     }
+    if not args.no_large:
+        line["large_grids"] = large_grids(L, I)
     if not args.no_serving:
         line["serving"] = serving_leg(L, I)
     if not args.no_cpu:

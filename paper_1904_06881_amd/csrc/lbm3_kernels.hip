@@ -739,22 +739,22 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
     };
     int my_cnt[3] = {0, 0, 0};
 
-    // PF: issue this plane's population loads before the field stage, so
-    // their latency overlaps the stencil work (registers permitting)
-    constexpr bool PF = D == 2;
-    constexpr int QF = PF ? Q : 1;
+    // This plane's f loads are issued before the field stage, so that their
+    // latency overlaps the stencil work; the g loads too where registers
+    // allow (2D), else (3D) after the f collision but before the f stores:
+    // loads and stores retire in order, so a load issued behind the stores
+    // would wait for them.
+    constexpr bool PG = D == 2;
     for (int p = pb; p < pe; ++p) {
         // the far ghost layer from plane p + 1, before this plane's loads
         if (GK && walls && p + 2 == nw - 1) ghost_plane(p + 2);
         const unsigned n = (unsigned)p * PS + nb[NIP / 2];
-        S fr[QF], gr[QF];
-        if constexpr (PF) {
-            if (active) {
+        S fr[Q], gr[PG ? Q : 1];
+        if (active) {
 #pragma unroll
-                for (int i = 0; i < Q; ++i) {
-                    fr[i] = fin[(size_t)i * N + n];
-                    gr[i] = gin[(size_t)i * N + n];
-                }
+            for (int i = 0; i < Q; ++i) {
+                fr[i] = fin[(size_t)i * N + n];
+                if constexpr (PG) gr[i] = gin[(size_t)i * N + n];
             }
         }
         commit(p + 2);
@@ -814,8 +814,7 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
             R j[3] = {0, 0, 0};
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
-                const S *fi = fin + (size_t)i * N;
-                f[i] = dec_f<PREC, D>(PF ? fr[PF ? i : 0] : fi[n], i, rp);
+                f[i] = dec_f<PREC, D>(fr[i], i, rp);
 #pragma unroll
                 for (int a = 0; a < D; ++a)
                     if (cdir(D, i, a) != 0) j[a] += (R)cdir(D, i, a) * f[i];
@@ -865,6 +864,13 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
                     for (int i = 0; i < Q; ++i) f[i] += ab * dl[i];
                 }
             }
+            // g populations (Eqs. 33-35 below), loaded ahead of the f stores
+            R gg[Q];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const S *gi = gin + (size_t)i * N;
+                gg[i] = dec_g<PREC, D>(PG ? gr[PG ? i : 0] : gi[n], i, pp);
+            }
             // stream f: push to x + c_i, halfway bounce-back at the walls
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
@@ -882,12 +888,6 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
                 }
             }
             // g: LBGK toward g^eq(phi, v) (Eqs. 33-35)
-            R gg[Q];
-#pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                const S *gi = gin + (size_t)i * N;
-                gg[i] = dec_g<PREC, D>(PF ? gr[PF ? i : 0] : gi[n], i, pp);
-            }
             if (collide) {
                 const R mup = s_t[t0][NP][tcen];
                 R vv = 0;
@@ -1258,11 +1258,14 @@ int launch_ghost(const KParams &kp, int prec, const Buffers &b, int fdst, void *
     return LBM3_CHECK_LAUNCH();
 }
 
-// chunk of march planes per block: enough blocks to fill the chip, at least
-// two planes so the ring prologue is amortised
-static int choose_chunk(long long tiles, int planes)
+// chunk of march planes per block: about `target` blocks, at least two
+// planes so the ring prologue is amortised.  Measured targets per tile class:
+// small 2D tiles (one wave each) run best with the most blocks; the 254-node
+// 2D tiles with one round of resident blocks (4 per CU); the 3D tiles (one
+// block per CU) with 8-plane chunks on a 256^3 grid.
+static int choose_chunk(int cls, long long tiles, int planes)
 {
-    const long long target = 2048;
+    const long long target = cls == 0 ? 2048 : (cls == 1 ? 1024 : 4096);
     long long c = (tiles * planes + target - 1) / target;
     if (c < 2) c = 2;
     if (c > 64) c = 64;
@@ -1292,7 +1295,7 @@ FusedGeom fused_geometry(const KParams &kp, int prec)
     int nty = kp.D == 3 ? (kp.ny + TY - 1) / TY : 1;
     int planes = kp.walls ? kp.nw - 2 : kp.nw;
     g.ntiles = ntx * nty;
-    g.chunk = choose_chunk((long long)g.ntiles, planes);
+    g.chunk = choose_chunk(g.cls, (long long)g.ntiles, planes);
     g.nchunks = (planes + g.chunk - 1) / g.chunk;
     return g;
 }
