@@ -76,7 +76,7 @@ int observe_blocks(const KParams &kp);
 // Batched launches over simulations of one class: blocks b = 0..nblocks-1
 // belong to simulation sim[b] of the device descriptor array d.
 FusedGeom fused_geometry(const KParams &kp, int prec);
-long long moments_blocks(const KParams &kp);
+long long moments_blocks(const KParams &kp, int prec);
 long long ghost_blocks(const KParams &kp);  // 0 when the step has no ghost launch
 int launch_moments_batch(int D, int prec, const SimDesc *d, const int *sim, long long nblocks, int phase,
                          void *stream);

@@ -300,7 +300,60 @@ __device__ __forceinline__ R entropic_alpha(const R *fp, R *dx, R eps, R tol, in
 }
 
 // -------------------------------------------------------------- moments --
-// rho, phi of fluid node number t (counted from the first fluid plane)
+// Nodes per thread of the moments kernel: in 2D, 16-byte loads of V
+// consecutive nodes when the plane stride is a multiple of V (then so are
+// the fluid range's start and length and every population array's offset);
+// in 3D one (27 wide loads per set outgrow the registers, measured slower).
+template <int D, int PREC> constexpr int mom_vec() { return D == 3 ? 1 : (PREC == P64 ? 2 : 4); }
+inline int mom_width(const KParams &kp, int prec)
+{
+    const int v = kp.D == 3 ? 1 : (prec == P64 ? 2 : 4);
+    return kp.PS % v == 0 ? v : 1;
+}
+
+// rho, phi of the fluid nodes of thread t (counted from the first fluid
+// plane): V nodes in one group, summed per node in population order
+template <int D, int PREC, int V>
+__device__ __forceinline__ void moments_nodes(const KParams &kp, const typename Ty<PREC>::S *__restrict__ f,
+                                              const typename Ty<PREC>::S *__restrict__ g,
+                                              const typename Ty<PREC>::R *__restrict__ rprev,
+                                              const typename Ty<PREC>::R *__restrict__ pprev,
+                                              typename Ty<PREC>::R *__restrict__ rho,
+                                              typename Ty<PREC>::R *__restrict__ phi, long long t)
+{
+    using R = typename Ty<PREC>::R;
+    using S = typename Ty<PREC>::S;
+    using VS = S __attribute__((ext_vector_type(V)));
+    using VR = R __attribute__((ext_vector_type(V)));
+    constexpr int Q = D == 2 ? 9 : 27;
+    const long long first = kp.walls ? kp.PS : 0;
+    const long long count = kp.walls ? kp.N - 2 * kp.PS : kp.N;
+    if (t * V >= count) return;
+    const long long n = first + t * V;
+    VR rp = (R)0, pp = (R)0;
+    if constexpr (PREC == P16) {
+        rp = *(const VR *)(rprev + n);
+        pp = *(const VR *)(pprev + n);
+    }
+    VS fv[Q], gv[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        fv[i] = *(const VS *)(f + (long long)i * kp.N + n);
+        gv[i] = *(const VS *)(g + (long long)i * kp.N + n);
+    }
+    VR r = (R)0, ph = (R)0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            r[j] += dec_f<PREC, D>(fv[i][j], i, rp[j]);
+            ph[j] += dec_g<PREC, D>(gv[i][j], i, pp[j]);
+        }
+    }
+    *(VR *)(rho + n) = r;
+    *(VR *)(phi + n) = ph;
+}
+
 template <int D, int PREC>
 __device__ __forceinline__ void moments_node(const KParams &kp, const typename Ty<PREC>::S *__restrict__ f,
                                              const typename Ty<PREC>::S *__restrict__ g,
@@ -309,22 +362,9 @@ __device__ __forceinline__ void moments_node(const KParams &kp, const typename T
                                              typename Ty<PREC>::R *__restrict__ rho,
                                              typename Ty<PREC>::R *__restrict__ phi, long long t)
 {
-    using R = typename Ty<PREC>::R;
-    constexpr int Q = D == 2 ? 9 : 27;
-    long long first = kp.walls ? kp.PS : 0;
-    long long count = kp.walls ? kp.N - 2 * kp.PS : kp.N;
-    if (t >= count) return;
-    long long n = first + t;
-    R rp = (R)0, pp = (R)0;
-    if constexpr (PREC == P16) { rp = rprev[n]; pp = pprev[n]; }
-    R r = 0, ph = 0;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        r += dec_f<PREC, D>(f[(long long)i * kp.N + n], i, rp);
-        ph += dec_g<PREC, D>(g[(long long)i * kp.N + n], i, pp);
-    }
-    rho[n] = r;
-    phi[n] = ph;
+    constexpr int V = mom_vec<D, PREC>();
+    if (kp.PS % V == 0) moments_nodes<D, PREC, V>(kp, f, g, rprev, pprev, rho, phi, t);
+    else moments_nodes<D, PREC, 1>(kp, f, g, rprev, pprev, rho, phi, t);
 }
 
 template <int D, int PREC>
@@ -602,36 +642,34 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
         if (walls && (q < 0 || q > nw - 1)) return false;
         return !(GK && walls && (q == 0 || q == nw - 1));
     };
-    R pre_r[NLD], pre_p[NLD];
-    auto fetch = [&](int q) {
+    auto fetch_into = [&](int q, R *dr, R *dp) {
         if (!has_fields(q)) return;
         const unsigned base = (unsigned)plane(q) * PS;
 #pragma unroll
         for (int m = 0; m < NLD; ++m) {
             int k = tid + m * NTH;
             if (NLD * NTH == FS || k < FS) {
-                pre_r[m] = rho[base + ld_idx[m]];
-                pre_p[m] = phi[base + ld_idx[m]];
+                dr[m] = rho[base + ld_idx[m]];
+                dp[m] = phi[base + ld_idx[m]];
             }
         }
     };
-    auto commit = [&](int q) {
+    auto commit_from = [&](int q, const R *dr, const R *dp) {
         if (!has_fields(q)) return;
         const int slot = (q + 10) % 5;
 #pragma unroll
         for (int m = 0; m < NLD; ++m) {
             int k = tid + m * NTH;
             if (NLD * NTH == FS || k < FS) {
-                s_r[slot][k] = pre_r[m];
-                if constexpr (QR) s_q[slot][k] = fsqrt(pre_r[m]);
-                s_p[slot][k] = pre_p[m];
+                s_r[slot][k] = dr[m];
+                if constexpr (QR) s_q[slot][k] = fsqrt(dr[m]);
+                s_p[slot][k] = dp[m];
             }
         }
     };
-    auto load_fields = [&](int q) {
-        fetch(q);
-        commit(q);
-    };
+    R pre_r[NLD], pre_p[NLD];
+    auto fetch = [&](int q) { fetch_into(q, pre_r, pre_p); };
+    auto commit = [&](int q) { commit_from(q, pre_r, pre_p); };
 
     // Wall ghost layer q (0 or nw - 1) over the tile and a halo of 2 (Sec. IV)
     // from the first fluid layer, which is in the ring; the wetting condition
@@ -707,8 +745,15 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
         }
     };
 
-    // prologue: fields pb-2 .. pb+1, -P planes pb-1 .. pb; plane pb+2 fetched
-    for (int q = pb - 2; q <= pb + 1; ++q) load_fields(q);
+    // prologue: fields pb-2 .. pb+1 (the four planes' loads in flight
+    // together), -P planes pb-1 .. pb; plane pb+2 fetched
+    {
+        R pr[4][NLD], pp[4][NLD];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) fetch_into(pb - 2 + j, pr[j], pp[j]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) commit_from(pb - 2 + j, pr[j], pp[j]);
+    }
     fetch(pb + 2);
     __syncthreads();
     if (GK && walls && (pb - 2 <= 0 || pb + 1 >= nw - 1)) {
@@ -1222,8 +1267,7 @@ static inline unsigned nblk(long long n, int t) { return (unsigned)((n + t - 1) 
 template <int D, int PREC>
 static int moments_t(const KParams &kp, const Buffers &b, int pc, int fc, hipStream_t st)
 {
-    long long count = kp.walls ? kp.N - 2 * kp.PS : kp.N;
-    k_moments<D, PREC><<<nblk(count, 256), 256, 0, st>>>(
+    k_moments<D, PREC><<<(unsigned)moments_blocks(kp, PREC), 256, 0, st>>>(
         kp, (SP<PREC>)b.f[pc], (SP<PREC>)b.g[pc], (RP<PREC>)b.rho[fc], (RP<PREC>)b.phi[fc],
         (RP<PREC>)b.rho[1 - fc], (RP<PREC>)b.phi[1 - fc]);
     return LBM3_CHECK_LAUNCH();
@@ -1334,10 +1378,11 @@ int launch_fused(const KParams &kp, int prec, const Buffers &b, int pc, int fc, 
 }
 
 // ------------------------------------------------------- batched launches
-long long moments_blocks(const KParams &kp)
+long long moments_blocks(const KParams &kp, int prec)
 {
-    long long count = kp.walls ? kp.N - 2 * kp.PS : kp.N;
-    return (count + 255) / 256;
+    const long long count = kp.walls ? kp.N - 2 * kp.PS : kp.N;
+    const int v = mom_width(kp, prec);
+    return ((count + v - 1) / v + 255) / 256;
 }
 
 long long ghost_blocks(const KParams &kp)
