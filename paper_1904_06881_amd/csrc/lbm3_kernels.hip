@@ -51,6 +51,11 @@ __device__ __forceinline__ int wrapi(int v, int n)
     return r < 0 ? r + n : r;
 }
 
+// a / b: correctly rounded in FP64; in FP32 a times the hardware reciprocal
+// (about 1 ulp), well inside the FP32 path's error budget
+template <typename R> __device__ __forceinline__ R fdiv(R a, R b) { return a / b; }
+template <> __device__ __forceinline__ float fdiv<float>(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+
 // Storage codecs.  FP16: f_i stored as f_i / (w_i rho_node) - 1 and the rest
 // g as g_0 - phi_node, with rho_node, phi_node the fields the writer holds
 // for the node the value is stored at; other g raw.
@@ -68,7 +73,7 @@ __device__ __forceinline__ typename Ty<PREC>::S enc_f(typename Ty<PREC>::R v, in
 {
     using S = typename Ty<PREC>::S;
     using R = typename Ty<PREC>::R;
-    if constexpr (PREC == P16) return (S)(v / ((R)wgt(D, i) * rn) - (R)1);
+    if constexpr (PREC == P16) return (S)(fdiv(v, (R)wgt(D, i) * rn) - (R)1);
     else return (S)v;
 }
 template <int PREC, int D>
@@ -106,10 +111,6 @@ template <typename R> struct Thermo {
 
 template <typename R> __device__ __forceinline__ R gfun(R x) { return x * (x - (R)0.5) * (x - (R)1); }
 
-// a / b: correctly rounded in FP64; in FP32 a times the hardware reciprocal
-// (about 1 ulp), well inside the FP32 path's error budget
-template <typename R> __device__ __forceinline__ R fdiv(R a, R b) { return a / b; }
-template <> __device__ __forceinline__ float fdiv<float>(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 // log1p: the library's in FP64; in FP32, for |y| < 0.28 the atanh series
 // 2 (s + s^3/3 + ... + s^9/9), s = y/(2 + y) (|s| < 0.14, truncation < 1e-9
 // relative), else the hardware log2 of 1 + y; about 3 ulp at worst
