@@ -62,7 +62,10 @@ enum { LBM3_WET_FORCE = 0, LBM3_WET_GEOM_INTERP = 1, LBM3_WET_GEOM_EXTRAP = 2 };
 enum { LBM3_FP64 = 0, LBM3_FP32 = 1, LBM3_FP16S = 2 };
 enum {
     LBM3_NO_COLLIDE = 1u,   /* streaming and bounce-back only */
-    LBM3_FORCE_ALPHA2 = 2u  /* alpha = 2 everywhere (BGK with 1/tau_f = 2 beta) */
+    LBM3_FORCE_ALPHA2 = 2u, /* alpha = 2 everywhere (BGK with 1/tau_f = 2 beta) */
+    LBM3_FUSED_3D = 4u      /* D3Q27: force, collision and streaming in one fused
+                               kernel instead of the default stencil pass plus
+                               collide kernel (same arithmetic) */
 };
 
 /* Problem statement (paper Sec. II-IV).  Zero-initialise, then set. */
@@ -91,7 +94,7 @@ typedef struct {
     int32_t precision;      /* LBM3_FP64, LBM3_FP32, LBM3_FP16S (FP32 arithmetic,
                                populations stored in FP16 as density-scaled
                                offsets from the lattice weights) */
-    uint32_t flags;         /* LBM3_NO_COLLIDE | LBM3_FORCE_ALPHA2 */
+    uint32_t flags;         /* LBM3_NO_COLLIDE | LBM3_FORCE_ALPHA2 | LBM3_FUSED_3D */
     double  alpha_eps;      /* small-deviation alpha below this max |Delta/f'|
                                (0: 1e-3 FP64, 1e-2 FP32 arithmetic) */
     double  alpha_tol;      /* Newton tolerance (0: 1e-10 FP64, 1e-5 FP32) */

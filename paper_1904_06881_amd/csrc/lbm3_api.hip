@@ -38,7 +38,7 @@ namespace {
 const double PI = 3.14159265358979323846;
 
 struct Layout {
-    size_t f[2], g[2], rho[2], phi[2], scratch, counters, partials, result, total;
+    size_t f[2], g[2], rho[2], phi[2], fmu, scratch, counters, partials, result, total;
 };
 
 int lattice_D(int32_t lattice) { return lattice == LBM3_D2Q9 ? 2 : (lattice == LBM3_D3Q27 ? 3 : 0); }
@@ -100,6 +100,7 @@ Layout layout(const lbm3_params *p)
     for (int k = 0; k < 2; ++k) L.g[k] = take((size_t)Q * N * s);
     for (int k = 0; k < 2; ++k) L.rho[k] = take((size_t)N * r);
     for (int k = 0; k < 2; ++k) L.phi[k] = take((size_t)N * r);
+    L.fmu = D == 3 ? take((size_t)(D + 1) * N * r) : 0;  // F, mu_phi of the two-kernel step
     L.scratch = take((size_t)N * 8);
     L.counters = take(8 * sizeof(unsigned long long));
     L.partials = take((size_t)1024 * 16 * sizeof(double));
@@ -224,6 +225,7 @@ lbm3_status lbm3_create(const lbm3_params *p, void *ws, size_t bytes, void *stre
         b.rho[i] = base + L.rho[i];
         b.phi[i] = base + L.phi[i];
     }
+    b.fmu = D == 3 ? (void *)(base + L.fmu) : nullptr;
     b.scratch = (double *)(base + L.scratch);
     b.counters = (unsigned long long *)(base + L.counters);
     b.partials = (double *)(base + L.partials);
@@ -548,7 +550,8 @@ static bool check_handles(lbm3 *const *hs, int n)
 }
 
 // launches of the batch: moments per (D, precision), ghost layers per
-// (D, precision) where the step has them, fused per (tile class, precision)
+// (D, precision) where the step has them, fused (or stencil) per (tile
+// class, precision), collide per (D, precision) for two-kernel 3D steps
 static void plan(lbm3 *const *hs, int n, std::vector<Launch> &L)
 {
     auto find = [&](int kind, int D, int prec, int cls) -> Launch & {
@@ -580,6 +583,12 @@ static void plan(lbm3 *const *hs, int n, std::vector<Launch> &L)
         Launch &f = find(2, k.D, prec, fg.cls);
         f.sims.push_back(i);
         f.prefix.push_back(f.prefix.back() + (long long)fg.ntiles * fg.nchunks);
+        long long cb = lbm3k::collide_blocks(k);
+        if (cb > 0) {
+            Launch &c = find(3, k.D, prec, 0);
+            c.sims.push_back(i);
+            c.prefix.push_back(c.prefix.back() + cb);
+        }
     }
     // kernel classes in step order
     std::stable_sort(L.begin(), L.end(), [](const Launch &a, const Launch &b) { return a.kind < b.kind; });
@@ -620,13 +629,14 @@ lbm3_status build(lbm3 *const *hs, int n, Image &img)
             s.rho[j] = h->b.rho[j];
             s.phi[j] = h->b.phi[j];
         }
+        s.fmu = h->b.fmu;
         s.counters = h->b.counters;
         s.pc = h->pc;
         s.fc = h->fc;
         FusedGeom fg = lbm3k::fused_geometry(h->kp, h->prec);
         s.chunk = fg.chunk;
         s.ntiles = fg.ntiles;
-        s.fblk0 = s.mblk0 = s.gblk0 = 0;
+        s.fblk0 = s.mblk0 = s.gblk0 = s.cblk0 = 0;
     }
     for (auto &l : img.launches) {
         int *t = (int *)(img.bytes.data() + l.table_off);
@@ -634,7 +644,7 @@ lbm3_status build(lbm3 *const *hs, int n, Image &img)
             int i = l.sims[k];
             long long b0 = l.prefix[k], b1 = l.prefix[k + 1];
             if (b1 > (long long)INT32_MAX) return LBM3_EINVAL;
-            (l.kind == 0 ? d[i].mblk0 : (l.kind == 1 ? d[i].gblk0 : d[i].fblk0)) = (int)b0;
+            (l.kind == 0 ? d[i].mblk0 : l.kind == 1 ? d[i].gblk0 : l.kind == 2 ? d[i].fblk0 : d[i].cblk0) = (int)b0;
             for (long long b = b0; b < b1; ++b) t[b] = i;
         }
     }
@@ -658,7 +668,8 @@ lbm3_status enqueue(lbm3 *const *hs, int m, const Image &img, const void *dev_ba
             const int *tab = (const int *)(base + l.table_off);
             int r = l.kind == 0 ? lbm3k::launch_moments_batch(l.D, l.prec, d, tab, nb, phase, stream)
                   : l.kind == 1 ? lbm3k::launch_ghost_batch(l.D, l.prec, d, tab, nb, phase, stream)
-                                : lbm3k::launch_fused_batch(l.cls, l.prec, d, tab, nb, phase, stream);
+                  : l.kind == 2 ? lbm3k::launch_fused_batch(l.cls, l.prec, d, tab, nb, phase, stream)
+                                : lbm3k::launch_collide_batch(l.D, l.prec, d, tab, nb, phase, stream);
             if (r) return LBM3_EDEVICE;
         }
     }

@@ -23,8 +23,10 @@ struct KParams {
     double kw[2][2];             // per wall: kappa_rho^w, kappa_phi^w
     double alpha_eps, alpha_tol;
     int alpha_maxit;
-    unsigned flags;              // 1 no-collide, 2 alpha = 2
+    unsigned flags;              // 1 no-collide, 2 alpha = 2, 4 one fused kernel in 3D
 };
+
+constexpr unsigned kFlagFused3D = 4u;
 
 enum Prec { P64 = 0, P32 = 1, P16 = 2 };
 
@@ -32,6 +34,7 @@ enum Prec { P64 = 0, P32 = 1, P16 = 2 };
 struct Buffers {
     void *f[2], *g[2];           // populations [Q][N], storage type by precision
     void *rho[2], *phi[2];       // fields [N], compute type
+    void *fmu;                   // 3D two-kernel step: F, mu_phi [D + 1][N], compute type
     double *scratch;             // N doubles (upload / export staging)
     unsigned long long *counters;// 4: newton, shortcut, fallback, spare
     double *partials;            // reduction partials
@@ -46,12 +49,15 @@ struct SimDesc {
     unsigned long long *counters;
     int pc, fc;               // buffer parities when the descriptors were written
     int chunk, ntiles;        // fused launch geometry of this simulation
-    int fblk0, mblk0, gblk0;  // its first block in the fused, moments and ghost launches
+    void *fmu;                // F, mu_phi of the 3D two-kernel step
+    int fblk0, mblk0, gblk0;  // its first block in the fused (or stencil), moments and ghost launches
+    int cblk0;                // and in the collide launch of the 3D two-kernel step
 };
 
 // Fused launch geometry of one simulation: tile class (0: 2D 62-node tiles,
-// 1: 2D 254-node tiles, 2: 3D 32x16 tiles (32x4 in FP64)), in-plane tiles,
-// planes per block and blocks along the wall axis.
+// 1: 2D 254-node tiles, 2: 3D 32x16 tiles (32x4 in FP64), 3: 3D 32x8 tiles
+// (32x4 in FP64) in the stencil pass of the two-kernel step), in-plane
+// tiles, planes per block and blocks along the wall axis.
 struct FusedGeom {
     int cls, ntiles, chunk, nchunks;
 };
@@ -62,6 +68,9 @@ int launch_ghost(const KParams &kp, int prec, const Buffers &b, int fdst, void *
 int launch_fused(const KParams &kp, int prec, const Buffers &b, int pc, int fc, void *stream);
 // true when the fused kernel fills the wall ghost layers itself (2D)
 bool fused_fills_ghost(const KParams &kp);
+// true when the step's last stage is the stencil pass plus the collide
+// kernel (3D unless the one-kernel flag is set)
+bool two_kernel_step(const KParams &kp);
 int launch_init(const KParams &kp, int prec, const Buffers &b, void *stream);
 int launch_init_field(const KParams &kp, int prec, const Buffers &b, int which, void *stream);
 int launch_observe(const KParams &kp, int prec, const Buffers &b, int pc, int fc, void *stream);
@@ -78,11 +87,14 @@ int observe_blocks(const KParams &kp);
 FusedGeom fused_geometry(const KParams &kp, int prec);
 long long moments_blocks(const KParams &kp, int prec);
 long long ghost_blocks(const KParams &kp);  // 0 when the step has no ghost launch
+long long collide_blocks(const KParams &kp);  // 0 unless the step is two-kernel
 int launch_moments_batch(int D, int prec, const SimDesc *d, const int *sim, long long nblocks, int phase,
                          void *stream);
 int launch_ghost_batch(int D, int prec, const SimDesc *d, const int *sim, long long nblocks, int phase,
                        void *stream);
 int launch_fused_batch(int cls, int prec, const SimDesc *d, const int *sim, long long nblocks, int phase,
                        void *stream);
+int launch_collide_batch(int D, int prec, const SimDesc *d, const int *sim, long long nblocks, int phase,
+                         void *stream);
 
 }  // namespace lbm3k
