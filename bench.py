@@ -39,13 +39,14 @@ PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_fused_d2q9_2048x64.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1904_06881_amd", "csrc", "lbm3_kernels.hip")
 
 
-def measured_traffic():
-    """HBM bytes per fused launch from the committed rocprofv3 counter
-    summary (FETCH_SIZE and WRITE_SIZE per dispatch, scaled by the copy
-    calibration), or None when the kernel source has changed since."""
+def measured_traffic(summary=PMC_SUMMARY, prefix="traffic"):
+    """HBM bytes per launch (per fused pass in the 3D two-kernel step) from a
+    committed rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE per
+    dispatch, scaled by the copy calibration), or None when the kernel
+    source has changed since the counters were taken."""
     import hashlib
     try:
-        text = open(PMC_SUMMARY).read()
+        text = open(summary).read()
         src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
     except OSError:
         return None
@@ -57,20 +58,22 @@ def measured_traffic():
     if kv.get("kernel_source_sha256") != src:
         return None
     try:
-        return 1024.0 * (float(kv["traffic_fetch_kib_per_dispatch"]) * float(kv["fetch_factor"]) +
-                         float(kv["traffic_write_kib_per_dispatch"]) * float(kv["write_factor"]))
+        return 1024.0 * (float(kv[prefix + "_fetch_kib_per_dispatch"]) * float(kv["fetch_factor"]) +
+                         float(kv[prefix + "_write_kib_per_dispatch"]) * float(kv["write_factor"]))
     except (KeyError, ValueError):
         return None
 
 
-def bytes_per_node(Q, s, sf, fp16):
+def bytes_per_node(Q, s, sf, fp16, two_kernel=False):
     """Algorithmic HBM bytes per fluid-node update.  Fused kernel: read and
     write both population sets (4 Q s) and read rho, phi (2 s_f), plus the
-    previous step's rho, phi for FP16 decoding.  Moments kernel: read both
-    sets (2 Q s), write rho, phi (2 s_f) (+ decode fields for FP16).  The
-    wall ghost layers (two rows) are left out."""
+    previous step's rho, phi for FP16 decoding.  The 3D two-kernel step
+    (stencil pass + collide) adds a second read of rho, phi and the write and
+    read of F, mu_phi (4 values in FP32).  Moments kernel: read both sets
+    (2 Q s), write rho, phi (2 s_f) (+ decode fields for FP16).  The wall
+    ghost layers are left out."""
     extra = 2 * sf if fp16 else 0
-    fused = 4 * Q * s + 2 * sf + extra
+    fused = 4 * Q * s + 2 * sf + extra + ((2 * sf + 2 * 4 * 4) if two_kernel else 0)
     moments = 2 * Q * s + 2 * sf + extra
     alg = 4 * Q * s + 4 * sf  # one read + one write of everything a step must touch
     return fused, moments, alg
@@ -104,6 +107,12 @@ LARGE = (
     ("d3q27_256cube_fp16s", "D3Q27", (256, 256, 256), "fp16s", 20, 5),
     ("d2q9_4096x256_fp32", "D2Q9", (4096, 256), "fp32", 400, 100),
 )
+# counter summaries of the same runs: (file, key prefix) per grid
+LARGE_PMC = {
+    "d3q27_256cube_fp32": (os.path.join(ROOT, "profiles", "k_collide_d3q27_256cube.md"), "traffic_fp32"),
+    "d3q27_256cube_fp16s": (os.path.join(ROOT, "profiles", "k_collide_d3q27_256cube.md"), "traffic_fp16s"),
+    "d2q9_4096x256_fp32": (os.path.join(ROOT, "profiles", "k_fused_d2q9_4096x256.md"), "traffic"),
+}
 
 
 def large_grids(L, I):
@@ -133,7 +142,7 @@ def large_grids(L, I):
         s.close()
         del s
         torch.cuda.empty_cache()
-        fb, mb, ab = bytes_per_node(Q, 2 if prec == "fp16s" else 4, 4, prec == "fp16s")
+        fb, mb, ab = bytes_per_node(Q, 2 if prec == "fp16s" else 4, 4, prec == "fp16s", two_kernel=Q == 27)
         fgbs = fb * fluid / (pr["fused"] * 1e-3) / 1e9
         mgbs = mb * fluid / (pr["moments"] * 1e-3) / 1e9
         out[name] = {"MLUPS": fluid * steps / wall / 1e6, "ms_per_step": 1e3 * wall / steps,
@@ -141,6 +150,7 @@ def large_grids(L, I):
                      "moments_ms": pr["moments"], "moments_GBs": mgbs, "moments_frac": mgbs / HBM_PEAK_GBS,
                      "bytes_per_node": {"fused": fb, "moments": mb, "step_min": ab},
                      "step_frac": fluid * steps / wall * ab / (HBM_PEAK_GBS * 1e9),
+                     "fused_traffic": measured_traffic(*LARGE_PMC[name]),
                      "n_bad": o["n_bad"]}
     return out
 

@@ -148,15 +148,16 @@ lbm3_status lbm3_init(lbm3 *h, const double *rho0, const double *phi0);
 /* Enqueue nsteps full updates on the handle's stream (asynchronous). */
 lbm3_status lbm3_step(lbm3 *h, int64_t nsteps);
 
-/* As lbm3_step, with HIP events recorded on the handle's stream around every
- * launch of every sample_every-th step (>= 1; LBM3_EINVAL otherwise), so that
- * the instrumentation leaves the other steps untouched; synchronises.
- * kernel_ms (host, 5 doubles, may be NULL) receives [0..2] the mean device
- * time per launch of the moments, ghost-layer and fused (stencil + collision
- * + streaming) kernels over the sampled steps (the ghost-layer entry is 0 in
- * 2D, where the fused kernel fills the ghost layers itself), [3] the time
- * from before the first to after the last step, and [4] the number of
- * sampled steps. */
+/* As lbm3_step, with HIP events recorded by the kernels of every
+ * sample_every-th step (>= 1; LBM3_EINVAL otherwise) from their own dispatch
+ * packets (start of a stage's first kernel, end of its last), so that no
+ * marker packet enters the stream; synchronises.  kernel_ms (host, 5
+ * doubles, may be NULL) receives [0..2] the mean device time per step of the
+ * three stages over the sampled steps: moments, ghost layers, and force +
+ * collision + streaming (the fused kernel, or in 3D the stencil pass plus
+ * the collide kernel); the ghost-layer entry is 0 in 2D, where the fused
+ * kernel fills the ghost layers itself; [3] the time from before the first
+ * to after the last step, and [4] the number of sampled steps. */
 lbm3_status lbm3_step_profiled(lbm3 *h, int64_t nsteps, int32_t sample_every, double *kernel_ms);
 
 /* Synchronise the stream and report the current state.  what: LBM3_OBS_*

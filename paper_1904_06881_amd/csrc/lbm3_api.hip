@@ -307,14 +307,17 @@ lbm3_status lbm3_step_profiled(lbm3 *h, int64_t nsteps, int32_t sample_every, do
     if (!h) return LBM3_EINVAL;
     if (!h->inited) return set_err(h, LBM3_ESTATE, "step before init");
     if (nsteps < 0 || sample_every < 1) return set_err(h, LBM3_EINVAL, "bad step count or sampling stride");
+    // per sampled step a start and a stop event for each of the three stages,
+    // recorded by the stage's own kernels (no marker packets between them)
     const int batch = 64;  // sampled steps between host synchronisations
-    hipEvent_t ev[4 * batch], first = nullptr, last = nullptr;
+    hipEvent_t ev[6 * batch], first = nullptr, last = nullptr;
     int made = 0;
     hipError_t e = hipSuccess;
     lbm3_status st = LBM3_OK;
     double acc[3] = {0, 0, 0}, span = 0;
     int64_t sampled = 0;
-    for (; made < 4 * batch; ++made)
+    const bool no_ghost = lbm3k::fused_fills_ghost(h->kp);
+    for (; made < 6 * batch; ++made)
         if ((e = hipEventCreate(&ev[made])) != hipSuccess) break;
     if (e == hipSuccess) e = hipEventCreate(&first);
     if (e == hipSuccess) e = hipEventCreate(&last);
@@ -323,15 +326,12 @@ lbm3_status lbm3_step_profiled(lbm3 *h, int64_t nsteps, int32_t sample_every, do
     int pending = 0;  // sampled steps whose events are not yet read
     auto drain = [&]() -> bool {
         if (!pending) return true;
-        if ((e = hipEventSynchronize(ev[4 * pending - 1])) != hipSuccess) return false;
+        if ((e = hipEventSynchronize(ev[6 * (pending - 1) + 5])) != hipSuccess) return false;
         for (int s = 0; s < pending; ++s)
             for (int j = 0; j < 3; ++j) {
-                // a step without the ghost-layer launch leaves E[2] unrecorded
-                const bool skip = lbm3k::fused_fills_ghost(h->kp);
-                if (j == 1 && skip) continue;
-                const int from = (j == 2 && skip) ? 1 : j;
+                if (j == 1 && no_ghost) continue;
                 float ms = 0;
-                if ((e = hipEventElapsedTime(&ms, ev[4 * s + from], ev[4 * s + j + 1])) != hipSuccess) return false;
+                if ((e = hipEventElapsedTime(&ms, ev[6 * s + 2 * j], ev[6 * s + 2 * j + 1])) != hipSuccess) return false;
                 acc[j] += ms;
             }
         sampled += pending;
@@ -340,18 +340,14 @@ lbm3_status lbm3_step_profiled(lbm3 *h, int64_t nsteps, int32_t sample_every, do
     };
     for (int64_t t = 0; t < nsteps && st == LBM3_OK; ++t) {
         const bool timed = t % sample_every == 0;
-        hipEvent_t *E = ev + 4 * pending;
+        hipEvent_t *E = ev + 6 * pending;
         int r = 0;
-        if (timed && (e = hipEventRecord(E[0], h->stream)) != hipSuccess) { st = hip_err(h, e, "event record"); break; }
         for (int j = 0; j < 3 && !r; ++j) {
-            if (j == 1 && lbm3k::fused_fills_ghost(h->kp)) continue;
+            if (j == 1 && no_ghost) continue;
+            if (timed) lbm3k::set_stage_events(E[2 * j], E[2 * j + 1]);
             r = launch_step(h, j);
-            if (!r && timed && (e = hipEventRecord(E[j + 1], h->stream)) != hipSuccess) {
-                st = hip_err(h, e, "event record");
-                break;
-            }
+            lbm3k::set_stage_events(nullptr, nullptr);
         }
-        if (st != LBM3_OK) break;
         if (r) { st = set_err(h, LBM3_EDEVICE, "kernel launch failed"); break; }
         h->pc ^= 1;
         h->fc ^= 1;

@@ -19,6 +19,7 @@
 //              LBGK and streaming (k_fused does all of it in 3D too when one
 //              kernel is asked for).
 // k_ghost also fills the ghost layers for initialisation and export.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "lbm3_internal.h"
@@ -1526,12 +1527,31 @@ template <int PREC> using RP = typename Ty<PREC>::R *;
 
 static inline unsigned nblk(long long n, int t) { return (unsigned)((n + t - 1) / t); }
 
+// Events of the stage a profiled step is launching: the stage's first
+// kernel records `start` and its last `stop` from their own dispatch packets
+// (hipExtLaunchKernelGGL), so the interval is the kernels' run time, without
+// a marker packet (and the dispatch gap that comes with it) in between.
+static thread_local hipEvent_t t_stage_start = nullptr, t_stage_stop = nullptr;
+
+void set_stage_events(void *start, void *stop)
+{
+    t_stage_start = (hipEvent_t)start;
+    t_stage_stop = (hipEvent_t)stop;
+}
+
+template <typename F, typename... A>
+static void stage_launch(F kernel, dim3 grid, dim3 block, hipStream_t st, bool first, bool last, A... args)
+{
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, st, first ? t_stage_start : nullptr,
+                          last ? t_stage_stop : nullptr, 0, args...);
+}
+
 template <int D, int PREC>
 static int moments_t(const KParams &kp, const Buffers &b, int pc, int fc, hipStream_t st)
 {
-    k_moments<D, PREC><<<(unsigned)moments_blocks(kp, PREC), 256, 0, st>>>(
-        kp, (SP<PREC>)b.f[pc], (SP<PREC>)b.g[pc], (RP<PREC>)b.rho[fc], (RP<PREC>)b.phi[fc],
-        (RP<PREC>)b.rho[1 - fc], (RP<PREC>)b.phi[1 - fc]);
+    stage_launch(k_moments<D, PREC>, dim3((unsigned)moments_blocks(kp, PREC)), dim3(256), st, true, true, kp,
+                 (SP<PREC>)b.f[pc], (SP<PREC>)b.g[pc], (RP<PREC>)b.rho[fc], (RP<PREC>)b.phi[fc],
+                 (RP<PREC>)b.rho[1 - fc], (RP<PREC>)b.phi[1 - fc]);
     return LBM3_CHECK_LAUNCH();
 }
 
@@ -1555,11 +1575,11 @@ int launch_ghost(const KParams &kp, int prec, const Buffers &b, int fdst, void *
     long long np = kp.D == 2 ? kp.nx : (long long)kp.nx * kp.ny;
     unsigned g = nblk(2 * np, 256);
     if (prec == P64) {
-        if (kp.D == 2) k_ghost<2, double><<<g, 256, 0, st>>>(kp, (double *)b.rho[fdst], (double *)b.phi[fdst]);
-        else k_ghost<3, double><<<g, 256, 0, st>>>(kp, (double *)b.rho[fdst], (double *)b.phi[fdst]);
+        if (kp.D == 2) stage_launch(k_ghost<2, double>, dim3(g), dim3(256), st, true, true, kp, (double *)b.rho[fdst], (double *)b.phi[fdst]);
+        else stage_launch(k_ghost<3, double>, dim3(g), dim3(256), st, true, true, kp, (double *)b.rho[fdst], (double *)b.phi[fdst]);
     } else {
-        if (kp.D == 2) k_ghost<2, float><<<g, 256, 0, st>>>(kp, (float *)b.rho[fdst], (float *)b.phi[fdst]);
-        else k_ghost<3, float><<<g, 256, 0, st>>>(kp, (float *)b.rho[fdst], (float *)b.phi[fdst]);
+        if (kp.D == 2) stage_launch(k_ghost<2, float>, dim3(g), dim3(256), st, true, true, kp, (float *)b.rho[fdst], (float *)b.phi[fdst]);
+        else stage_launch(k_ghost<3, float>, dim3(g), dim3(256), st, true, true, kp, (float *)b.rho[fdst], (float *)b.phi[fdst]);
     }
     return LBM3_CHECK_LAUNCH();
 }
@@ -1616,10 +1636,9 @@ static int fused_t(const KParams &kp, const Buffers &b, int pc, int fc, hipStrea
 {
     FusedGeom g = fused_geometry(kp, PREC);
     dim3 grid((unsigned)g.ntiles, (unsigned)g.nchunks);
-    k_fused<D, PREC, TX, TY, NTH><<<grid, NTH, 0, st>>>(
-        kp, (SP<PREC>)b.f[pc], (SP<PREC>)b.g[pc], (SP<PREC>)b.f[1 - pc], (SP<PREC>)b.g[1 - pc],
-        (RP<PREC>)b.rho[1 - fc], (RP<PREC>)b.phi[1 - fc], (RP<PREC>)b.rho[fc], (RP<PREC>)b.phi[fc],
-        b.counters, g.chunk);
+    stage_launch(k_fused<D, PREC, TX, TY, NTH>, grid, dim3(NTH), st, true, true, kp, (SP<PREC>)b.f[pc],
+                 (SP<PREC>)b.g[pc], (SP<PREC>)b.f[1 - pc], (SP<PREC>)b.g[1 - pc], (RP<PREC>)b.rho[1 - fc],
+                 (RP<PREC>)b.phi[1 - fc], (RP<PREC>)b.rho[fc], (RP<PREC>)b.phi[fc], b.counters, g.chunk);
     return LBM3_CHECK_LAUNCH();
 }
 
@@ -1630,14 +1649,14 @@ static int split_t(const KParams &kp, const Buffers &b, int pc, int fc, hipStrea
 {
     FusedGeom g = fused_geometry(kp, PREC);
     dim3 grid((unsigned)g.ntiles, (unsigned)g.nchunks);
-    k_stencil<3, PREC, TX, TY, NTH><<<grid, NTH, 0, st>>>(kp, (RP<PREC>)b.rho[1 - fc], (RP<PREC>)b.phi[1 - fc],
-                                                          (RP<PREC>)b.fmu, g.chunk);
+    stage_launch(k_stencil<3, PREC, TX, TY, NTH>, grid, dim3(NTH), st, true, false, kp, (RP<PREC>)b.rho[1 - fc],
+                 (RP<PREC>)b.phi[1 - fc], (RP<PREC>)b.fmu, g.chunk);
     int r = LBM3_CHECK_LAUNCH();
     if (r) return r;
-    k_collide<3, PREC><<<(unsigned)collide_blocks(kp), 256, 0, st>>>(
-        kp, (SP<PREC>)b.f[pc], (SP<PREC>)b.g[pc], (SP<PREC>)b.f[1 - pc], (SP<PREC>)b.g[1 - pc],
-        (RP<PREC>)b.rho[1 - fc], (RP<PREC>)b.phi[1 - fc], (RP<PREC>)b.rho[fc], (RP<PREC>)b.phi[fc],
-        (RP<PREC>)b.fmu, b.counters);
+    stage_launch(k_collide<3, PREC>, dim3((unsigned)collide_blocks(kp)), dim3(256), st, false, true, kp,
+                 (SP<PREC>)b.f[pc], (SP<PREC>)b.g[pc], (SP<PREC>)b.f[1 - pc], (SP<PREC>)b.g[1 - pc],
+                 (RP<PREC>)b.rho[1 - fc], (RP<PREC>)b.phi[1 - fc], (RP<PREC>)b.rho[fc], (RP<PREC>)b.phi[fc],
+                 (RP<PREC>)b.fmu, b.counters);
     return LBM3_CHECK_LAUNCH();
 }
 
