@@ -163,8 +163,15 @@ SERVE_N, SERVE_RATE, SERVE_STEPS, SERVE_QUANTUM = 48, 16.0, (250, 1000), 50
 SERVE_POOL = 24 << 30
 
 
-def serving_requests(L, I):
-    reqs = I.serving_requests(SERVE_N, seed=2024, rate=SERVE_RATE, steps=SERVE_STEPS)
+def serving_requests(L, I, burst=False):
+    if burst:
+        # burst: small D2Q9 requests (64^2..256^2) all arriving at once
+        reqs = I.serving_requests(SERVE_N, seed=2025, rate=SERVE_RATE, frac_2d=1.0, grid2=(64, 256),
+                                  steps=SERVE_STEPS)
+        for q in reqs:
+            q["arrival"] = 0.0
+    else:
+        reqs = I.serving_requests(SERVE_N, seed=2024, rate=SERVE_RATE, steps=SERVE_STEPS)
     for q in reqs:
         lat = L.D2Q9 if q["lattice"] == "D2Q9" else L.D3Q27
         prec = L.FP32 if q["precision"] == "fp32" else L.FP16S
@@ -225,15 +232,11 @@ def run_plain(L, reqs):
     return lat, time.perf_counter() - t0, ok
 
 
-def serving_leg(L, I):
-    reqs = serving_requests(L, I)
+def _compare(L, reqs):
     total = sum(q["updates"] for q in reqs)
     lat_s, span_s, ok_s = run_serving(L, reqs)
     lat_p, span_p, ok_p = run_plain(L, reqs)
     return {
-        "workload": "%d requests of the serving stream (seed 2024): Poisson arrivals %.0f/s, 70%% D2Q9 64^2..1024^2, "
-                    "30%% D3Q27 64^3..192^3, sessile drops theta 30..150 deg, gamma 0.005..0.03, FP32 / FP16-offset "
-                    "storage, %d..%d steps (full stream / 20)" % (SERVE_N, SERVE_RATE, SERVE_STEPS[0], SERVE_STEPS[1]),
         "node_updates": total,
         "batched": {"MLUPS": total / span_s / 1e6, "makespan_s": span_s, "p50_s": _pct(lat_s, 50),
                     "p99_s": _pct(lat_s, 99), "ok": ok_s, "quantum": SERVE_QUANTUM, "pool_bytes": SERVE_POOL},
@@ -241,6 +244,19 @@ def serving_leg(L, I):
                   "p99_s": _pct(lat_p, 99), "ok": ok_p},
         "throughput_ratio": span_p / span_s,
     }
+
+
+def serving_leg(L, I):
+    out = _compare(L, serving_requests(L, I))
+    out["workload"] = ("%d requests of the serving stream (seed 2024): Poisson arrivals %.0f/s, 70%% D2Q9 "
+                       "64^2..1024^2, 30%% D3Q27 64^3..192^3, sessile drops theta 30..150 deg, gamma 0.005..0.03, "
+                       "FP32 / FP16-offset storage, %d..%d steps (full stream / 20)"
+                       % (SERVE_N, SERVE_RATE, SERVE_STEPS[0], SERVE_STEPS[1]))
+    burst = _compare(L, serving_requests(L, I, burst=True))
+    burst["workload"] = ("burst: %d D2Q9 requests 64^2..256^2 (seed 2025) arriving together, otherwise as the "
+                         "stream" % SERVE_N)
+    out["burst"] = burst
+    return out
 
 
 def cpu_baseline(target_s=12.0):
