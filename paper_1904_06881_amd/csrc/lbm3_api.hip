@@ -102,7 +102,7 @@ Layout layout(const lbm3_params *p)
     for (int k = 0; k < 2; ++k) L.phi[k] = take((size_t)N * r);
     L.fmu = D == 3 ? take((size_t)(D + 1) * N * r) : 0;  // F, mu_phi of the two-kernel step
     L.scratch = take((size_t)N * 8);
-    L.counters = take(8 * sizeof(unsigned long long));
+    L.counters = take((size_t)lbm3k::kCntSlots * lbm3k::kCntStride * sizeof(unsigned long long));
     L.partials = take((size_t)1024 * 16 * sizeof(double));
     L.result = take(32 * sizeof(double));
     L.total = off;
@@ -266,7 +266,8 @@ lbm3_status lbm3_init(lbm3 *h, const double *rho0, const double *phi0)
     }
     if (lbm3k::launch_ghost(k, h->prec, h->b, 0, h->stream)) return set_err(h, LBM3_EDEVICE, "ghost launch failed");
     if (lbm3k::launch_init(k, h->prec, h->b, h->stream)) return set_err(h, LBM3_EDEVICE, "init launch failed");
-    if ((e = hipMemsetAsync(h->b.counters, 0, 8 * sizeof(unsigned long long), h->stream)) != hipSuccess)
+    if ((e = hipMemsetAsync(h->b.counters, 0, (size_t)lbm3k::kCntSlots * lbm3k::kCntStride * sizeof(unsigned long long),
+                            h->stream)) != hipSuccess)
         return hip_err(h, e, "counters");
     if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return hip_err(h, e, "init");
     h->pc = h->fc = 0;
@@ -416,11 +417,15 @@ lbm3_status lbm3_observe(lbm3 *h, uint32_t what, lbm3_obs *out, double *rho_out,
         if (lbm3k::launch_observe(k, h->prec, h->b, h->pc, h->fc, h->stream))
             return set_err(h, LBM3_EDEVICE, "observe launch failed");
         double r[16];
-        unsigned long long c[4];
+        std::vector<unsigned long long> slots((size_t)lbm3k::kCntSlots * lbm3k::kCntStride);
         if ((e = hipMemcpyAsync(r, h->b.result, sizeof(r), hipMemcpyDeviceToHost, h->stream)) != hipSuccess ||
-            (e = hipMemcpyAsync(c, h->b.counters, sizeof(c), hipMemcpyDeviceToHost, h->stream)) != hipSuccess)
+            (e = hipMemcpyAsync(slots.data(), h->b.counters, slots.size() * sizeof(unsigned long long),
+                                hipMemcpyDeviceToHost, h->stream)) != hipSuccess)
             return hip_err(h, e, "observe download");
         if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return hip_err(h, e, "observe");
+        unsigned long long c[3] = {0, 0, 0};
+        for (int k = 0; k < lbm3k::kCntSlots; ++k)
+            for (int q = 0; q < 3; ++q) c[q] += slots[(size_t)k * lbm3k::kCntStride + q];
         for (int q = 0; q < 3; ++q) out->mass[q] = r[q];
         out->rho_sum = r[3];
         out->phi_sum = r[4];

@@ -28,6 +28,11 @@ struct KParams {
 
 constexpr unsigned kFlagFused3D = 4u;
 
+// alpha statistics: blocks add into one of kCntSlots slots (by block index),
+// each a 128-byte line, so a launch's atomics do not queue on one address;
+// the reader sums the slots
+constexpr int kCntSlots = 64, kCntStride = 16;
+
 enum Prec { P64 = 0, P32 = 1, P16 = 2 };
 
 // Device buffers of one simulation, carved out of the caller's workspace.
@@ -36,7 +41,7 @@ struct Buffers {
     void *rho[2], *phi[2];       // fields [N], compute type
     void *fmu;                   // 3D two-kernel step: F, mu_phi [D + 1][N], compute type
     double *scratch;             // N doubles (upload / export staging)
-    unsigned long long *counters;// 4: newton, shortcut, fallback, spare
+    unsigned long long *counters;// kCntSlots slots of kCntStride: newton, shortcut, fallback
     double *partials;            // reduction partials
     double *result;              // 32 doubles of reduced observables
     int n_partials;              // capacity in blocks

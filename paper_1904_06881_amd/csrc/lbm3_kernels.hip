@@ -1049,7 +1049,8 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
     if (my_cnt[1]) atomicAdd(&s_cnt[1], my_cnt[1]);
     if (my_cnt[2]) atomicAdd(&s_cnt[2], my_cnt[2]);
     __syncthreads();
-    if (tid < 3 && s_cnt[tid]) atomicAdd(&cnt[tid], (unsigned long long)s_cnt[tid]);
+    if (tid < 3 && s_cnt[tid])
+        atomicAdd(&cnt[(size_t)((bx + by * 7) & (kCntSlots - 1)) * kCntStride + tid], (unsigned long long)s_cnt[tid]);
 }
 
 #define LBM3_FUSED_ATTR                                                                                     \
@@ -1246,7 +1247,9 @@ k_collide(KParams kp, const typename Ty<PREC>::S *__restrict__ fin, const typena
     if (t < count) kind = collide_node<D, PREC>(kp, fin, gin, fout, gout, rho, phi, rprev, pprev, fmu, t);
     count_kinds(kind, s_cnt);
     __syncthreads();
-    if (threadIdx.x < 3 && s_cnt[threadIdx.x]) atomicAdd(&cnt[threadIdx.x], (unsigned long long)s_cnt[threadIdx.x]);
+    if (threadIdx.x < 3 && s_cnt[threadIdx.x])
+        atomicAdd(&cnt[(size_t)(blockIdx.x & (kCntSlots - 1)) * kCntStride + threadIdx.x],
+                  (unsigned long long)s_cnt[threadIdx.x]);
 }
 
 template <int D, int PREC>
@@ -1271,7 +1274,8 @@ k_collide_batch(const SimDesc *__restrict__ d, const int *__restrict__ sim, int 
     count_kinds(kind, s_cnt);
     __syncthreads();
     if (threadIdx.x < 3 && s_cnt[threadIdx.x])
-        atomicAdd(&sd.counters[threadIdx.x], (unsigned long long)s_cnt[threadIdx.x]);
+        atomicAdd(&sd.counters[(size_t)(blockIdx.x & (kCntSlots - 1)) * kCntStride + threadIdx.x],
+                  (unsigned long long)s_cnt[threadIdx.x]);
 }
 
 // ---------------------------------------------------------------- init ---
