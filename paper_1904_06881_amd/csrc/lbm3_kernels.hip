@@ -629,11 +629,11 @@ k_ghost_batch(const SimDesc *__restrict__ d, const int *__restrict__ sim, int ph
 // ---------------------------------------------------------------- fused --
 // wrap of v into [0, n) for |v| < 2n (one conditional each way)
 // Planes [pb, pe) of block row `by` along the wall axis.  In the small 2D
-// class the six planes next to each wall run one per block: they hold the
-// wetting films' interfaces (most Newton solves of alpha) and the ghost
-// fill, and with every block of such a launch resident at once the slowest
-// block sets its duration (measured 6 % faster on a 2048 x 64 channel than
-// uniform two-plane chunks, 3 % with three planes, slower with ten).
+// class, when its chunks hold more than one plane, the six planes next to
+// each wall run one per block: they hold the wetting films' interfaces (most
+// Newton solves of alpha) and the ghost fill, and with every block of such a
+// launch resident at once the slowest block sets its duration (measured 6 %
+// faster than uniform two-plane chunks on a 2048 x 64 channel).
 __host__ __device__ inline int wall_edge(const KParams &kp, bool small2d, int chunk)
 {
     const int planes = kp.walls ? kp.nw - 2 : kp.nw;
@@ -1588,16 +1588,18 @@ int launch_ghost(const KParams &kp, int prec, const Buffers &b, int fdst, void *
     return LBM3_CHECK_LAUNCH();
 }
 
-// chunk of march planes per block: about `target` blocks, at least two
-// planes so the ring prologue is amortised.  Measured targets per tile class:
-// small 2D tiles (one wave each) run best with the most blocks; the 254-node
-// 2D tiles with one round of resident blocks (4 per CU); the 3D tiles (one
-// block per CU) with 8-plane chunks on a 256^3 grid.
+// chunk of march planes per block: about `target` blocks.  Measured per tile
+// class: the small 2D tiles (one wave each, all resident at once) run best
+// with one plane per block up to 8192 blocks (2048 x 64: 9 % faster than two
+// planes); the 254-node 2D tiles with one round of resident blocks (4 per
+// CU) and at least two planes, so the ring prologue is amortised; the 3D
+// tiles with 8-plane chunks on a 256^3 grid.
 static int choose_chunk(int cls, long long tiles, int planes)
 {
-    const long long target = cls == 0 ? 2048 : (cls == 1 ? 1024 : 4096);
+    const long long target = cls == 0 ? 8192 : (cls == 1 ? 1024 : 4096);
+    const long long cmin = cls == 0 ? 1 : 2;
     long long c = (tiles * planes + target - 1) / target;
-    if (c < 2) c = 2;
+    if (c < cmin) c = cmin;
     if (c > 64) c = 64;
     if (c > planes) c = planes;
     return (int)c;
