@@ -452,6 +452,16 @@ k_moments(KParams kp, const typename Ty<PREC>::S *__restrict__ f, const typename
     moments_node<D, PREC>(kp, f, g, rprev, pprev, rho, phi, (long long)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
+// A buffer pointer read from a simulation descriptor, re-derived from the
+// descriptor array (a kernel argument, known to be global memory) so that
+// the accesses through it compile to global instead of flat instructions
+// (flat ones also count against the LDS wait counter): the same address.
+template <typename T>
+__device__ __forceinline__ T *on_global(const SimDesc *base, const void *p)
+{
+    return (T *)((const char *)base + (long long)((uintptr_t)p - (uintptr_t)base));
+}
+
 // One launch over many simulations: block b belongs to simulation sim[b];
 // `phase` is the number of steps taken since the descriptors were written.
 template <int D, int PREC>
@@ -463,8 +473,9 @@ k_moments_batch(const SimDesc *__restrict__ d, const int *__restrict__ sim, int 
     const SimDesc &sd = d[sim[blockIdx.x]];
     const KParams &kp = sd.kp;
     const int pc = sd.pc ^ phase, fc = sd.fc ^ phase;
-    moments_node<D, PREC>(kp, (const S *)sd.f[pc], (const S *)sd.g[pc], (const R *)sd.rho[fc], (const R *)sd.phi[fc],
-                          (R *)sd.rho[1 - fc], (R *)sd.phi[1 - fc],
+    moments_node<D, PREC>(kp, on_global<const S>(d, sd.f[pc]), on_global<const S>(d, sd.g[pc]),
+                          on_global<const R>(d, sd.rho[fc]), on_global<const R>(d, sd.phi[fc]),
+                          on_global<R>(d, sd.rho[1 - fc]), on_global<R>(d, sd.phi[1 - fc]),
                           (long long)(blockIdx.x - sd.mblk0) * blockDim.x + threadIdx.x);
 }
 
@@ -623,7 +634,8 @@ k_ghost_batch(const SimDesc *__restrict__ d, const int *__restrict__ sim, int ph
     const SimDesc &sd = d[sim[blockIdx.x]];
     const KParams &kp = sd.kp;
     const int fc = sd.fc ^ phase;
-    ghost_node<D, R>(kp, (R *)sd.rho[1 - fc], (R *)sd.phi[1 - fc], (blockIdx.x - sd.gblk0) * blockDim.x + threadIdx.x);
+    ghost_node<D, R>(kp, on_global<R>(d, sd.rho[1 - fc]), on_global<R>(d, sd.phi[1 - fc]),
+                     (blockIdx.x - sd.gblk0) * blockDim.x + threadIdx.x);
 }
 
 // ---------------------------------------------------------------- fused --
@@ -1079,9 +1091,11 @@ k_fused_batch(const SimDesc *__restrict__ d, const int *__restrict__ sim, int ph
     const KParams &kp = sd.kp;
     const int pc = sd.pc ^ phase, fc = sd.fc ^ phase;
     const int local = blockIdx.x - sd.fblk0;
-    fused_tile<D, PREC, TX, TY, NTH>(kp, (const S *)sd.f[pc], (const S *)sd.g[pc], (S *)sd.f[1 - pc], (S *)sd.g[1 - pc],
-                                     (R *)sd.rho[1 - fc], (R *)sd.phi[1 - fc], (const R *)sd.rho[fc],
-                                     (const R *)sd.phi[fc], sd.counters, sd.chunk, local % sd.ntiles,
+    fused_tile<D, PREC, TX, TY, NTH>(kp, on_global<const S>(d, sd.f[pc]), on_global<const S>(d, sd.g[pc]),
+                                     on_global<S>(d, sd.f[1 - pc]), on_global<S>(d, sd.g[1 - pc]),
+                                     on_global<R>(d, sd.rho[1 - fc]), on_global<R>(d, sd.phi[1 - fc]),
+                                     on_global<const R>(d, sd.rho[fc]), on_global<const R>(d, sd.phi[fc]),
+                                     on_global<unsigned long long>(d, sd.counters), sd.chunk, local % sd.ntiles,
                                      local / sd.ntiles);
 }
 
@@ -1105,9 +1119,9 @@ k_stencil_batch(const SimDesc *__restrict__ d, const int *__restrict__ sim, int 
     const KParams &kp = sd.kp;
     const int fc = sd.fc ^ phase;
     const int local = blockIdx.x - sd.fblk0;
-    fused_tile<D, PREC, TX, TY, NTH, true>(kp, nullptr, nullptr, nullptr, nullptr, (R *)sd.rho[1 - fc],
-                                           (R *)sd.phi[1 - fc], nullptr, nullptr, nullptr, sd.chunk,
-                                           local % sd.ntiles, local / sd.ntiles, (R *)sd.fmu);
+    fused_tile<D, PREC, TX, TY, NTH, true>(kp, nullptr, nullptr, nullptr, nullptr, on_global<R>(d, sd.rho[1 - fc]),
+                                           on_global<R>(d, sd.phi[1 - fc]), nullptr, nullptr, nullptr, sd.chunk,
+                                           local % sd.ntiles, local / sd.ntiles, on_global<R>(d, sd.fmu));
 }
 
 // Collision and push streaming of fluid node number t (counted from the
@@ -1268,13 +1282,16 @@ k_collide_batch(const SimDesc *__restrict__ d, const int *__restrict__ sim, int 
     const long long t = (long long)(blockIdx.x - sd.cblk0) * blockDim.x + threadIdx.x;
     int kind = -1;
     if (t < count)
-        kind = collide_node<D, PREC>(kp, (const S *)sd.f[pc], (const S *)sd.g[pc], (S *)sd.f[1 - pc],
-                                     (S *)sd.g[1 - pc], (const R *)sd.rho[1 - fc], (const R *)sd.phi[1 - fc],
-                                     (const R *)sd.rho[fc], (const R *)sd.phi[fc], (const R *)sd.fmu, t);
+        kind = collide_node<D, PREC>(kp, on_global<const S>(d, sd.f[pc]), on_global<const S>(d, sd.g[pc]),
+                                     on_global<S>(d, sd.f[1 - pc]), on_global<S>(d, sd.g[1 - pc]),
+                                     on_global<const R>(d, sd.rho[1 - fc]), on_global<const R>(d, sd.phi[1 - fc]),
+                                     on_global<const R>(d, sd.rho[fc]), on_global<const R>(d, sd.phi[fc]),
+                                     on_global<const R>(d, sd.fmu), t);
     count_kinds(kind, s_cnt);
     __syncthreads();
     if (threadIdx.x < 3 && s_cnt[threadIdx.x])
-        atomicAdd(&sd.counters[(size_t)(blockIdx.x & (kCntSlots - 1)) * kCntStride + threadIdx.x],
+        atomicAdd(&on_global<unsigned long long>(d, sd.counters)[(size_t)(blockIdx.x & (kCntSlots - 1)) * kCntStride +
+                                                               threadIdx.x],
                   (unsigned long long)s_cnt[threadIdx.x]);
 }
 
