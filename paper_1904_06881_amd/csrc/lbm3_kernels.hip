@@ -815,12 +815,14 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
             if (NLD * NTH != FS && k >= FS) continue;
             const int lx = k % FW, ly = k / FW;
             if (lx < HF - 2 || lx >= FW - HF + 2 || (D == 3 && (ly < HF - 2 || ly >= FH - HF + 2))) continue;
+            // the LDS read is unconditional (clamped index) and the global
+            // one overrides it, so the two are not merged into one flat load
             auto get = [&](int dx, int dy, R &r, R &ph) {
                 const int jx = lx + dx, jy = ly + dy;
-                if (jx >= 0 && jx < FW && jy >= 0 && jy < FH) {
-                    r = s_r[sf][jy * FW + jx];
-                    ph = s_p[sf][jy * FW + jx];
-                } else {
+                const int cx = jx < 0 ? 0 : (jx >= FW ? FW - 1 : jx), cy = jy < 0 ? 0 : (jy >= FH ? FH - 1 : jy);
+                r = s_r[sf][cy * FW + cx];
+                ph = s_p[sf][cy * FW + cx];
+                if (jx != cx || jy != cy) {
                     unsigned n = bf + (unsigned)wrapl(x0 + jx - HF, nx);
                     if constexpr (D == 3) n += (unsigned)nx * (unsigned)wrapl(y0 + jy - HF, ny);
                     r = rho[n];
