@@ -320,6 +320,25 @@ def test_cfg4_full_size_fp32_one_step():
     assert err <= 1e-5
 
 
+def test_fp64_small_tiles_multi_plane_chunks():
+    """A small-tile 2D grid large enough for multi-plane chunks (1024 x 600:
+    17 x 598 tile planes, two planes per block, the six planes next to each
+    wall one per block) with drops on both walls: FP64 after 12 steps
+    against the oracle."""
+    nx, ny = 1024, 600
+    r1, p1 = I.sessile_drop_2d(nx, ny, 60, xc=300.0)
+    # a second drop hanging from the top wall (mirrored rows)
+    r2, p2 = I.sessile_drop_2d(nx, ny, 45, xc=700.0, comp=3)
+    rho0 = np.where(np.abs(r1 - r1[0, 0]) > 1e-12, r1, r2[::-1])
+    phi0 = np.where(np.abs(r1 - r1[0, 0]) > 1e-12, p1, p2[::-1])
+    p = L.make_params(L.D2Q9, (nx, ny), gamma=(0.01, 0.012, 0.009), width=4.0,
+                      theta_deg=[[60.0, 60.0, 60.0], [120.0, 120.0, 120.0]], precision=L.FP64)
+    sim, ora = run_both(p, rho0, phi0, 12)
+    err = conc_err(sim, ora)
+    say("1024x600 fp64 err", err)
+    assert err <= 1e-11
+
+
 def test_cfg3_full_size_properties():
     """Config 3 at full size (256^3, FP32 and FP16 storage): 20 steps stay
     finite, conserve the component masses to FP32 summation accuracy."""
