@@ -913,7 +913,8 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
     auto nbi = [&](int i) -> unsigned {
         return D == 3 ? nb[(cdir(D, i, 0) + 1) * 3 + cdir(D, i, 1) + 1] : nb[cdir(D, i, 0) + 1];
     };
-    int my_cnt[3] = {0, 0, 0};
+    // alpha kinds of the wave's nodes, counted per plane with ballots
+    unsigned long long wave_cnt[3] = {0, 0, 0};
 
     // This plane's f loads are issued before the field stage, so that their
     // latency overlaps the stencil work; the g loads too where registers
@@ -938,6 +939,7 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
         __syncthreads();
         compute_T(p + 1);
         __syncthreads();
+        int kind_p = -1;
         if (active) {
             const int sm = (p + 9) % 5, s0 = (p + 10) % 5, sp = (p + 11) % 5;
             const int tm = (p + 9) % 3, t0 = (p + 10) % 3, tp = (p + 11) % 3;
@@ -1009,10 +1011,7 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
                     ud[a] = u[a] + du;
                     v[a] = u[a] + (R)0.5 * du;
                 }
-                if (collide) {
-                    const int kind = collide_f<D, R>(f, r0, u, ud, beta, aeps, atol, kp.alpha_maxit, alpha2);
-                    if (kind >= 0) my_cnt[kind == 1 ? 0 : (kind == 0 ? 1 : 2)]++;
-                }
+                if (collide) kind_p = collide_f<D, R>(f, r0, u, ud, beta, aeps, atol, kp.alpha_maxit, alpha2);
                 // g populations (Eqs. 33-35 below), loaded ahead of the f stores
                 R gg[Q];
 #pragma unroll
@@ -1055,16 +1054,28 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
                 }
             }
         }
+        if constexpr (!SPLIT) {
+            wave_cnt[0] += __popcll(__ballot(kind_p == 1));
+            wave_cnt[1] += __popcll(__ballot(kind_p == 0));
+            wave_cnt[2] += __popcll(__ballot(kind_p == 2));
+        }
         __syncthreads();
     }
     if constexpr (SPLIT) return;
-    // alpha statistics
-    if (my_cnt[0]) atomicAdd(&s_cnt[0], my_cnt[0]);
-    if (my_cnt[1]) atomicAdd(&s_cnt[1], my_cnt[1]);
-    if (my_cnt[2]) atomicAdd(&s_cnt[2], my_cnt[2]);
-    __syncthreads();
-    if (tid < 3 && s_cnt[tid])
-        atomicAdd(&cnt[(size_t)((bx + by * 7) & (kCntSlots - 1)) * kCntStride + tid], (unsigned long long)s_cnt[tid]);
+    // alpha statistics: one add per wave and kind (a one-wave block adds to
+    // its counter slot directly)
+    unsigned long long *slot = cnt + (size_t)((bx + by * 7) & (kCntSlots - 1)) * kCntStride;
+    if constexpr (NTH <= 64) {
+        if (tid < 3 && wave_cnt[tid == 0 ? 0 : (tid == 1 ? 1 : 2)])
+            atomicAdd(&slot[tid], wave_cnt[tid == 0 ? 0 : (tid == 1 ? 1 : 2)]);
+    } else {
+        if ((tid & 63) == 0)
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                if (wave_cnt[k]) atomicAdd(&s_cnt[k], (int)wave_cnt[k]);
+        __syncthreads();
+        if (tid < 3 && s_cnt[tid]) atomicAdd(&slot[tid], (unsigned long long)s_cnt[tid]);
+    }
 }
 
 #define LBM3_FUSED_ATTR                                                                                     \
