@@ -307,34 +307,93 @@ __device__ __forceinline__ R entropic_alpha(const R *fp, R *dx, R eps, R tol, in
 }
 
 // ------------------------------------------------------------ collision --
+// Per-axis equilibrium factors at u and at u + du and their differences
+// (FP32).  With s = sqrt(1 + 3u^2), A = 2 - s and B = (2u + s)/(1 - u)
+// (Eq. 27) the factors (A/6B, 2A/3, AB/6) sum to 1 and their first moment
+// is u exactly; in FP32 the c = -1 factor is computed and the others are
+// taken from these two identities, so that the equilibrium carries the
+// node's mass and momentum to rounding (computed through A and B their
+// errors bias both, by 1e-8 per step).  The c = -1 difference is formed
+// without cancellation: A(u + du) - A(u) = -3 du (2u + du)/(s + s') and
+// B(u + du) - B(u) = (2 du + (s' - s)(1 - u) + s du)/((1 - u)(1 - u - du)).
+template <typename R>
+__device__ __forceinline__ void feq_factor_steps(R u, R du, R *fe, R *fd, R *dd)
+{
+    // no contraction into fused multiply-adds, so that every kernel that
+    // inlines this rounds it the same way
+#pragma clang fp contract(off)
+    const R ud = u + du;
+    const R s = fsqrt((R)1 + (R)3 * u * u), sd = fsqrt((R)1 + (R)3 * ud * ud);
+    const R A = (R)2 - s;
+    const R B = fdiv((R)2 * u + s, (R)1 - u), Bd = fdiv((R)2 * ud + sd, (R)1 - ud);
+    const R dA = fdiv((R)-3 * du * ((R)2 * u + du), s + sd);
+    const R dB = fdiv((R)2 * du - dA * ((R)1 - u) + s * du, ((R)1 - u) * ((R)1 - ud));
+    fe[0] = fdiv((R)(1.0 / 6.0) * A, B);
+    dd[0] = fdiv((R)(1.0 / 6.0) * (dA * B - A * dB), B * Bd);
+    fd[0] = fe[0] + dd[0];
+    fe[2] = fe[0] + u;
+    fd[2] = fd[0] + ud;
+    dd[2] = dd[0] + du;
+    fe[1] = (R)1 - fe[0] - fe[2];
+    fd[1] = (R)1 - fd[0] - fd[2];
+    dd[1] = -(dd[0] + dd[2]);
+}
+
 // ELBM step of one node (Eqs. 24-32): on entry f holds the node's stored
 // populations, on return f* = f' + alpha beta Delta, with the mirror state
-// f' = f + f^eq(rho, u + du) - f^eq(rho, u) and Delta = f^eq(rho, u + du) - f'.
-// Returns the alpha kind (0 small deviation, 1 Newton, 2 fallback), or -1
-// when alpha = 2 is forced.
+// f' = f + f^eq(rho, u + du) - f^eq(rho, u) and Delta = f^eq(rho, u + du) - f'
+// = f^eq(rho, u) - f.  Returns the alpha kind (0 small deviation, 1 Newton,
+// 2 fallback), or -1 when alpha = 2 is forced.
 template <int D, typename R>
-__device__ __forceinline__ int collide_f(R *f, R r0, const R *u, const R *ud, R beta, R aeps, R atol, int maxit,
+__device__ __forceinline__ int collide_f(R *f, R r0, const R *u, const R *du, R beta, R aeps, R atol, int maxit,
                                          bool alpha2)
 {
     constexpr int Q = D == 2 ? 9 : 27;
-    R fe[3][3], fd[3][3];
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-        feq_factors(u[a], fe[a]);
-        feq_factors(ud[a], fd[a]);
-    }
     R dl[Q];
+    if constexpr (sizeof(R) == 4) {
+        // FP32: the forcing term f^eq(u + du) - f^eq(u) is small against
+        // either equilibrium, so it is formed from the factor differences
+        // (a telescoping product) instead of subtracting two rounded
+        // equilibria; Delta as f^eq(u) - f.  Not contracted into fused
+        // multiply-adds, so that every kernel rounds it the same way.
+#pragma clang fp contract(off)
+        R fe[3][3], fd[3][3], dd[3][3];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        R e = r0 * fe[0][cdir(D, i, 0) + 1] * fe[1][cdir(D, i, 1) + 1];
-        R d = r0 * fd[0][cdir(D, i, 0) + 1] * fd[1][cdir(D, i, 1) + 1];
-        if constexpr (D == 3) {
-            e *= fe[2][cdir(D, i, 2) + 1];
-            d *= fd[2][cdir(D, i, 2) + 1];
+        for (int a = 0; a < D; ++a) feq_factor_steps(u[a], du[a], fe[a], fd[a], dd[a]);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int kx = cdir(D, i, 0) + 1, ky = cdir(D, i, 1) + 1, kz = D == 3 ? cdir(D, i, 2) + 1 : 1;
+            R e, dme;
+            if constexpr (D == 3) {
+                e = r0 * fe[0][kx] * fe[1][ky] * fe[2][kz];
+                dme = r0 * (dd[0][kx] * fd[1][ky] * fd[2][kz] + fe[0][kx] * (dd[1][ky] * fd[2][kz] +
+                                                                              fe[1][ky] * dd[2][kz]));
+            } else {
+                e = r0 * fe[0][kx] * fe[1][ky];
+                dme = r0 * (dd[0][kx] * fd[1][ky] + fe[0][kx] * dd[1][ky]);
+            }
+            dl[i] = e - f[i];  // Delta
+            f[i] += dme;       // mirror state f'
         }
-        R fpi = f[i] + d - e;
-        dl[i] = d - fpi;  // Delta
-        f[i] = fpi;       // mirror state f'
+    } else {
+        R fe[3][3], fd[3][3];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            feq_factors(u[a], fe[a]);
+            feq_factors(u[a] + du[a], fd[a]);
+        }
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            R e = r0 * fe[0][cdir(D, i, 0) + 1] * fe[1][cdir(D, i, 1) + 1];
+            R d = r0 * fd[0][cdir(D, i, 0) + 1] * fd[1][cdir(D, i, 1) + 1];
+            if constexpr (D == 3) {
+                e *= fe[2][cdir(D, i, 2) + 1];
+                d *= fd[2][cdir(D, i, 2) + 1];
+            }
+            R fpi = f[i] + d - e;
+            dl[i] = d - fpi;  // Delta
+            f[i] = fpi;       // mirror state f'
+        }
     }
     R al = (R)2;
     bool is_x = false;
@@ -1014,16 +1073,15 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
                     for (int a = 0; a < D; ++a)
                         if (cdir(D, i, a) != 0) j[a] += (R)cdir(D, i, a) * f[i];
                 }
-                R u[3], ud[3], v[3];
+                R u[3], du[3], v[3];
                 const R ir = (R)1 / r0;
 #pragma unroll
                 for (int a = 0; a < D; ++a) {
                     u[a] = j[a] * ir;
-                    R du = F[a] * ir;
-                    ud[a] = u[a] + du;
-                    v[a] = u[a] + (R)0.5 * du;
+                    du[a] = F[a] * ir;
+                    v[a] = u[a] + (R)0.5 * du[a];
                 }
-                if (collide) kind_p = collide_f<D, R>(f, r0, u, ud, beta, aeps, atol, kp.alpha_maxit, alpha2);
+                if (collide) kind_p = collide_f<D, R>(f, r0, u, du, beta, aeps, atol, kp.alpha_maxit, alpha2);
                 // g populations (Eqs. 33-35 below), loaded ahead of the f stores
                 R gg[Q];
 #pragma unroll
@@ -1214,17 +1272,16 @@ __device__ __forceinline__ int collide_node(const KParams &kp, const typename Ty
         for (int a = 0; a < D; ++a)
             if (cdir(D, i, a) != 0) j[a] += (R)cdir(D, i, a) * f[i];
     }
-    R u[3], ud[3], v[3];
+    R u[3], du[3], v[3];
     const R ir = (R)1 / r0;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
         u[a] = j[a] * ir;
-        R du = F[a] * ir;
-        ud[a] = u[a] + du;
-        v[a] = u[a] + (R)0.5 * du;
+        du[a] = F[a] * ir;
+        v[a] = u[a] + (R)0.5 * du[a];
     }
     int kind = -1;
-    if (collide) kind = collide_f<D, R>(f, r0, u, ud, beta, (R)kp.alpha_eps, (R)kp.alpha_tol, kp.alpha_maxit, alpha2);
+    if (collide) kind = collide_f<D, R>(f, r0, u, du, beta, (R)kp.alpha_eps, (R)kp.alpha_tol, kp.alpha_maxit, alpha2);
     // g loads ahead of the f stores (loads and stores retire in order)
     R gg[Q];
 #pragma unroll

@@ -206,13 +206,13 @@ def test_force_kw0_equals_geometric90_gpu():
 
 
 # ------------------------------------------------------ precision forms ---
-@pytest.mark.parametrize("prec,tol", [(L.FP32, 1.5e-3), (L.FP16S, 2e-3)])
+@pytest.mark.parametrize("prec,tol", [(L.FP32, 1e-4), (L.FP16S, 2e-3)])
 def test_reduced_precision_2000_steps_cfg1(prec, tol):
     """P2: FP32 arithmetic (FP32 or FP16-offset population storage) against
-    the FP64 oracle after 2000 steps of config 1.  Measured: FP32 2.3e-4,
-    FP16 storage 6.7e-4, both at the contact line in the first fluid layer and
-    growing with time (a slow drift of the contact-line position); the bulk
-    and the free interface agree to ~1e-5."""
+    the FP64 oracle after 2000 steps of config 1, at the stated tolerances
+    (max-abs C_k <= 1e-4 FP32, <= 2e-3 FP16 storage; contact angle within 1
+    degree).  Measured: FP32 8.6e-5, FP16 storage 3.3e-4, largest at the
+    contact line in the first fluid layer."""
     rho0, phi0 = I.sessile_drop_2d(128, 64, 20, xc=64)
     sim, ora = run_both(cfg1_params(precision=prec), rho0, phi0, 2000)
     err = conc_err(sim, ora)
@@ -227,14 +227,6 @@ def test_reduced_precision_2000_steps_cfg1(prec, tol):
     ao = O.contact_angle_2d(conc(ro, po, d.rho_l, d.rho_g)[1], exclude=8.0)[0]
     say("cfg1 prec", prec, "contact angle", ag, "oracle", ao)
     assert abs(ag - ao) < 1.0
-
-
-@pytest.mark.xfail(reason="FP32 target of 1e-4 after 2000 steps not met: the contact line "
-                          "drifts slowly (max-abs C_k 2.3e-4)", strict=False)
-def test_fp32_target_1e4_cfg1():
-    rho0, phi0 = I.sessile_drop_2d(128, 64, 20, xc=64)
-    sim, ora = run_both(cfg1_params(precision=L.FP32), rho0, phi0, 2000)
-    assert conc_err(sim, ora) <= 1e-4
 
 
 def test_mass_conservation_gpu_fp64():
