@@ -621,11 +621,26 @@ __device__ __forceinline__ void interp3(Get get, R lx, R ly, R &r, R &ph)
     ph = plane3(X, Y, Cp, lx, ly);
 }
 
+// cot(theta) of the three interface pairs at one wall, in registers: the
+// empty asm keeps the compiler from turning the selects back into an indexed
+// load from the parameter block (a memory access and a wait per use)
+template <typename R>
+__device__ __forceinline__ void wall_cots(const KParams &kp, int wall, R (&c)[3])
+{
+    R a0 = (R)kp.cot[0][0], a1 = (R)kp.cot[0][1], a2 = (R)kp.cot[0][2];
+    R b0 = (R)kp.cot[1][0], b1 = (R)kp.cot[1][1], b2 = (R)kp.cot[1][2];
+    asm volatile("" : "+v"(a0), "+v"(a1), "+v"(a2), "+v"(b0), "+v"(b1), "+v"(b2));
+    c[0] = wall == 0 ? a0 : b0;
+    c[1] = wall == 0 ? a1 : b1;
+    c[2] = wall == 0 ? a2 : b2;
+}
+
 // Ghost-layer values of one wall node (Sec. IV): copy of the first fluid
 // layer for the force method, else the geometric wetting condition with the
-// contact angle of the interface found by the detection rules.
+// contact angle of the interface found by the detection rules (cot: the
+// wall's cot(theta) per pair, from wall_cots).
 template <int D, typename R, typename Get>
-__device__ __forceinline__ void ghost_value(const KParams &kp, int wall, Get get, R &out_r, R &out_p)
+__device__ __forceinline__ void ghost_value(const KParams &kp, const R (&cot)[3], Get get, R &out_r, R &out_p)
 {
     R r0, p0;
     get(0, 0, r0, p0);
@@ -650,7 +665,7 @@ __device__ __forceinline__ void ghost_value(const KParams &kp, int wall, Get get
     if (ngr < (R)1e-12 * drho && ngp < (R)1e-12 * drho) return;
     R dot = gr[0] * gp[0] + gr[1] * gp[1];
     int cls = classify(ngr, ngp, dot, r0, p0, (R)kp.rho_l, drho, chi);
-    R ct = (R)kp.cot[wall][cls];
+    const R ct = cls == 0 ? cot[0] : (cls == 1 ? cot[1] : cot[2]);
     const R *gc = cls == 2 ? gp : gr;
     R ngc = cls == 2 ? ngp : ngr;
     if (kp.wetting == 2) {
@@ -685,8 +700,9 @@ __device__ __forceinline__ void ghost_node(const KParams &kp, R *__restrict__ rh
         r = rho[n];
         ph = phi[n];
     };
-    R out_r, out_p;
-    ghost_value<D, R>(kp, wall, get, out_r, out_p);
+    R out_r, out_p, cot[3];
+    wall_cots<R>(kp, wall, cot);
+    ghost_value<D, R>(kp, cot, get, out_r, out_p);
     rho[ng] = out_r;
     phi[ng] = out_p;
 }
@@ -717,14 +733,25 @@ k_ghost_batch(const SimDesc *__restrict__ d, const int *__restrict__ sim, int ph
 // Newton solves of alpha) and the ghost fill, and with every block of such a
 // launch resident at once the slowest block sets its duration (measured 6 %
 // faster than uniform two-plane chunks on a 2048 x 64 channel).
+//
+// With one plane per block (chunk 1) the same small 2D class instead takes
+// the two planes next to each wall first (edge -1): those blocks fill the
+// ghost layers and run longest, and blocks start in index order.
 __host__ __device__ inline int wall_edge(const KParams &kp, bool small2d, int chunk)
 {
     const int planes = kp.walls ? kp.nw - 2 : kp.nw;
+    if (small2d && kp.walls && chunk == 1 && planes >= 4) return -1;
     return (small2d && kp.walls && chunk > 1 && planes > 12 + chunk) ? 6 : 0;
 }
 __host__ __device__ inline void chunk_range(const KParams &kp, int edge, int chunk, int by, int &pb, int &pe)
 {
     const int pf0 = kp.walls ? 1 : 0, pf1 = kp.walls ? kp.nw - 1 : kp.nw;
+    if (edge < 0) {
+        // planes 1, nw - 2, 2, nw - 3, then 3 .. nw - 4
+        pb = by < 4 ? ((by & 1) ? kp.nw - 2 - (by >> 1) : 1 + (by >> 1)) : by - 1;
+        pe = pb + 1;
+        return;
+    }
     if (edge == 0) {
         pb = pf0 + by * chunk;
         pe = pb + chunk < pf1 ? pb + chunk : pf1;
@@ -745,6 +772,7 @@ __host__ __device__ inline void chunk_range(const KParams &kp, int edge, int chu
 __host__ __device__ inline int chunk_count(const KParams &kp, int edge, int chunk)
 {
     const int planes = kp.walls ? kp.nw - 2 : kp.nw;
+    if (edge < 0) return planes;
     return edge ? 2 * edge + (planes - 2 * edge + chunk - 1) / chunk : (planes + chunk - 1) / chunk;
 }
 
@@ -767,7 +795,9 @@ __device__ __forceinline__ int wrapl(int v, int n)
 // SPLIT: the stencil pass of the two-kernel step instead (3D): the same
 // march and force, then F and mu_phi go to fmu ([D + 1][N]) and the
 // populations are left to k_collide.
-template <int D, int PREC, int TX, int TY, int NTH, bool SPLIT = false>
+// ONE: every chunk is one plane (no march loop, so the compiler's counts of
+// memory operations in flight need not merge a loop's back edge).
+template <int D, int PREC, int TX, int TY, int NTH, bool SPLIT = false, bool ONE = false>
 __device__ __forceinline__ void
 fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, const typename Ty<PREC>::S *__restrict__ gin,
            typename Ty<PREC>::S *__restrict__ fout, typename Ty<PREC>::S *__restrict__ gout,
@@ -821,11 +851,14 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
 #pragma unroll
     for (int m = 0; m < NLD; ++m) {
         int k = tid + m * NTH;
-        int lx = k % FW, ly = k / FW;
+        // threads beyond the tile's elements load the last element again
+        // (one address, so their loads cost one cache line per wave)
+        const int ka = k < FS ? k : FS - 1;
+        int lx = ka % FW, ly = ka / FW;
         unsigned v = (unsigned)wrapl(x0 + lx - HF, nx);
         if constexpr (D == 3) v += (unsigned)nx * (unsigned)wrapl(y0 + ly - HF, ny);
         ld_idx[m] = v;
-        bool o = k < FS && lx >= HF && lx < TX + HF && x0 + lx - HF < nx;
+        bool o = k < FS && lx >= HF && lx < TX + HF && x0 + lx - HF < nx;  // k >= FS: not own
         if constexpr (D == 3) o = o && ly >= HF && ly < TY + HF && y0 + ly - HF < ny;
         own |= (o ? 1u : 0u) << m;
     }
@@ -837,21 +870,23 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
 
     // plane q of rho, phi into the LDS ring (ghost layers: ghost_plane), in
     // two halves: fetch issues the loads into registers, commit stores them,
-    // so a plane's loads can be in flight while the previous one is worked on
+    // so a plane's loads can be in flight while the previous one is worked on.
+    // Every thread loads, whether or not the element is used (planes beyond
+    // the walls read the nearest stored plane, surplus threads the tile's
+    // last element): with no load under a branch the compiler's counts of
+    // loads in flight stay exact, and a wait for one plane does not also wait
+    // for the loads issued after it.
     auto has_fields = [&](int q) {
         if (walls && (q < 0 || q > nw - 1)) return false;
         return !(GK && walls && (q == 0 || q == nw - 1));
     };
     auto fetch_into = [&](int q, R *dr, R *dp) {
-        if (!has_fields(q)) return;
-        const unsigned base = (unsigned)plane(q) * PS;
+        const int qc = walls ? (q < 0 ? 0 : (q > nw - 1 ? nw - 1 : q)) : q;
+        const unsigned base = (unsigned)plane(qc) * PS;
 #pragma unroll
         for (int m = 0; m < NLD; ++m) {
-            int k = tid + m * NTH;
-            if (NLD * NTH == FS || k < FS) {
-                dr[m] = rho[base + ld_idx[m]];
-                dp[m] = phi[base + ld_idx[m]];
-            }
+            dr[m] = rho[base + ld_idx[m]];
+            dp[m] = phi[base + ld_idx[m]];
         }
     };
     auto commit_from = [&](int q, const R *dr, const R *dp) {
@@ -873,43 +908,58 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
 
     // Wall ghost layer q (0 or nw - 1) over the tile and a halo of 2 (Sec. IV)
     // from the first fluid layer, which is in the ring; the wetting condition
-    // reads it within the tile's halo of HF = 3 from LDS and further out along
-    // the wall (contact angles far from 90 degrees) from rho, phi.
+    // reads it within the tile's halo of HF = 3 from LDS and, where a contact
+    // angle's |cot| exceeds 1 (interpolation shifts beyond one node), further
+    // out along the wall from rho, phi.  The two cases are separate code, so
+    // that the common one has no global loads (whose waits would also wait
+    // for the population loads in flight).
     auto ghost_plane = [&](int q) {
         if constexpr (!GK) return;
         const int wall = q == 0 ? 0 : 1;
         const int kf = wall == 0 ? 1 : nw - 2;
         const int sg = (q + 10) % 5, sf = (kf + 10) % 5;
         const unsigned bf = (unsigned)kf * PS, bg = (unsigned)q * PS;
-        for (int m = 0; m < NLD; ++m) {
-            const int k = tid + m * NTH;
-            if (NLD * NTH != FS && k >= FS) continue;
-            const int lx = k % FW, ly = k / FW;
-            if (lx < HF - 2 || lx >= FW - HF + 2 || (D == 3 && (ly < HF - 2 || ly >= FH - HF + 2))) continue;
-            // the LDS read is unconditional (clamped index) and the global
-            // one overrides it, so the two are not merged into one flat load
-            auto get = [&](int dx, int dy, R &r, R &ph) {
-                const int jx = lx + dx, jy = ly + dy;
-                const int cx = jx < 0 ? 0 : (jx >= FW ? FW - 1 : jx), cy = jy < 0 ? 0 : (jy >= FH ? FH - 1 : jy);
-                r = s_r[sf][cy * FW + cx];
-                ph = s_p[sf][cy * FW + cx];
-                if (jx != cx || jy != cy) {
-                    unsigned n = bf + (unsigned)wrapl(x0 + jx - HF, nx);
-                    if constexpr (D == 3) n += (unsigned)nx * (unsigned)wrapl(y0 + jy - HF, ny);
-                    r = rho[n];
-                    ph = phi[n];
+        R cot[3];
+        wall_cots<R>(kp, wall, cot);
+        const bool far = kp.wetting == 1 && (fabs(cot[0]) > (R)1 || fabs(cot[1]) > (R)1 || fabs(cot[2]) > (R)1);
+        auto run = [&](auto far_t) {
+            constexpr bool FAR = decltype(far_t)::value;
+            for (int m = 0; m < NLD; ++m) {
+                const int k = tid + m * NTH;
+                if (NLD * NTH != FS && k >= FS) continue;
+                const int lx = k % FW, ly = k / FW;
+                if (lx < HF - 2 || lx >= FW - HF + 2 || (D == 3 && (ly < HF - 2 || ly >= FH - HF + 2))) continue;
+                // the LDS read is unconditional (clamped index) and the global
+                // one overrides it, so the two are not merged into one flat load
+                auto get = [&](int dx, int dy, R &r, R &ph) {
+                    const int jx = lx + dx, jy = ly + dy;
+                    const int cx = jx < 0 ? 0 : (jx >= FW ? FW - 1 : jx), cy = jy < 0 ? 0 : (jy >= FH ? FH - 1 : jy);
+                    r = s_r[sf][cy * FW + cx];
+                    ph = s_p[sf][cy * FW + cx];
+                    if constexpr (FAR) {
+                        if (jx != cx || jy != cy) {
+                            unsigned n = bf + (unsigned)wrapl(x0 + jx - HF, nx);
+                            if constexpr (D == 3) n += (unsigned)nx * (unsigned)wrapl(y0 + jy - HF, ny);
+                            r = rho[n];
+                            ph = phi[n];
+                        }
+                    }
+                };
+                R gr_, gp_;
+                ghost_value<D, R>(kp, cot, get, gr_, gp_);
+                s_r[sg][k] = gr_;
+                if constexpr (QR) s_q[sg][k] = fsqrt(gr_);
+                s_p[sg][k] = gp_;
+                if (own & (1u << m)) {
+                    rho[bg + ld_idx[m]] = gr_;
+                    phi[bg + ld_idx[m]] = gp_;
                 }
-            };
-            R gr_, gp_;
-            ghost_value<D, R>(kp, wall, get, gr_, gp_);
-            s_r[sg][k] = gr_;
-            if constexpr (QR) s_q[sg][k] = fsqrt(gr_);
-            s_p[sg][k] = gp_;
-            if (own & (1u << m)) {
-                rho[bg + ld_idx[m]] = gr_;
-                phi[bg + ld_idx[m]] = gp_;
             }
-        }
+        };
+        if (far)
+            run(std::true_type{});
+        else
+            run(std::false_type{});
     };
 
     auto compute_T = [&](int q) {
@@ -947,31 +997,13 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
         }
     };
 
-    // prologue: fields pb-2 .. pb+1 (the four planes' loads in flight
-    // together), -P planes pb-1 .. pb; plane pb+2 fetched
-    {
-        R pr[4][NLD], pp[4][NLD];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) fetch_into(pb - 2 + j, pr[j], pp[j]);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) commit_from(pb - 2 + j, pr[j], pp[j]);
-    }
-    fetch(pb + 2);
-    __syncthreads();
-    if (GK && walls && (pb - 2 <= 0 || pb + 1 >= nw - 1)) {
-        for (int q = pb - 2; q <= pb + 1; ++q)
-            if (q == 0 || q == nw - 1) ghost_plane(q);
-        __syncthreads();
-    }
-    compute_T(pb - 1);
-    compute_T(pb);
-
     const int tx = tid % TX, ty = tid / TX;
     const int x = x0 + tx, y = y0 + ty;
     const bool active = tid < TX * TY && x < nx && (D == 2 || y < ny);
     const int fcen = (D == 3 ? (ty + HF) * FW : 0) + tx + HF;
     const int tcen = (D == 3 ? (ty + 1) * TW : 0) + tx + 1;
-    // in-plane indices of x + (cx, cy) for every in-plane offset
+    // in-plane indices of x + (cx, cy) for every in-plane offset (surplus
+    // threads take the last node of the row, so their addresses stay valid)
     unsigned nb[NIP];
 #pragma unroll
     for (int k = 0; k < NIP; ++k) {
@@ -980,6 +1012,45 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
         if constexpr (D == 3) v += (unsigned)nx * (unsigned)wrap1(min(y, ny - 1) + cy, ny);
         nb[k] = v;
     }
+
+    // This plane's f loads are issued before the field stage, so that their
+    // latency overlaps the stencil work; the g loads too where registers
+    // allow (2D), else (3D) after the f collision but before the f stores:
+    // loads and stores retire in order, so a load issued behind the stores
+    // would wait for them.  Every thread loads (inactive ones a valid node).
+    constexpr bool PG = D == 2;
+    S fr[Q], gr[PG ? Q : 1];
+    auto load_pops = [&](int p) {
+        if constexpr (!SPLIT) {
+            const unsigned n = (unsigned)p * PS + nb[NIP / 2];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                fr[i] = fin[(size_t)i * N + n];
+                if constexpr (PG) gr[i] = gin[(size_t)i * N + n];
+            }
+        }
+    };
+
+    // prologue: fields pb-2 .. pb+2 (the five planes' loads in flight
+    // together), -P planes pb-1 .. pb.  (Issuing the first plane's
+    // populations here as well measured slower on a 2048 x 64 channel:
+    // 38 loads per thread in flight at the kernel's start.)
+    {
+        R pr[4][NLD], pp[4][NLD];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) fetch_into(pb - 2 + j, pr[j], pp[j]);
+        fetch(pb + 2);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) commit_from(pb - 2 + j, pr[j], pp[j]);
+    }
+    __syncthreads();
+    if (GK && walls && (pb - 2 <= 0 || pb + 1 >= nw - 1)) {
+        for (int q = pb - 2; q <= pb + 1; ++q)
+            if (q == 0 || q == nw - 1) ghost_plane(q);
+        __syncthreads();
+    }
+    compute_T(pb - 1);
+    compute_T(pb);
     // in-plane index of population i's target
     auto nbi = [&](int i) -> unsigned {
         return D == 3 ? nb[(cdir(D, i, 0) + 1) * 3 + cdir(D, i, 1) + 1] : nb[cdir(D, i, 0) + 1];
@@ -987,26 +1058,14 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
     // alpha kinds of the wave's nodes, counted per plane with ballots
     unsigned long long wave_cnt[3] = {0, 0, 0};
 
-    // This plane's f loads are issued before the field stage, so that their
-    // latency overlaps the stencil work; the g loads too where registers
-    // allow (2D), else (3D) after the f collision but before the f stores:
-    // loads and stores retire in order, so a load issued behind the stores
-    // would wait for them.
-    constexpr bool PG = D == 2;
+    if (ONE) pe = pb + 1;
     for (int p = pb; p < pe; ++p) {
         // the far ghost layer from plane p + 1, before this plane's loads
         if (GK && walls && p + 2 == nw - 1) ghost_plane(p + 2);
         const unsigned n = (unsigned)p * PS + nb[NIP / 2];
-        S fr[Q], gr[PG ? Q : 1];
-        if (!SPLIT && active) {
-#pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                fr[i] = fin[(size_t)i * N + n];
-                if constexpr (PG) gr[i] = gin[(size_t)i * N + n];
-            }
-        }
+        load_pops(p);
         commit(p + 2);
-        if (p + 1 < pe) fetch(p + 3);
+        if (!ONE && p + 1 < pe) fetch(p + 3);
         __syncthreads();
         compute_T(p + 1);
         __syncthreads();
@@ -1152,7 +1211,7 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
     __launch_bounds__(NTH)                                                                                  \
     __attribute__((amdgpu_waves_per_eu(D == 3 ? (PREC == P64 ? 1 : 2) : (PREC == P64 ? 2 : (NTH <= 64 ? 3 : 4)))))
 
-template <int D, int PREC, int TX, int TY, int NTH>
+template <int D, int PREC, int TX, int TY, int NTH, bool ONE = false>
 __global__ void LBM3_FUSED_ATTR
 k_fused(KParams kp, const typename Ty<PREC>::S *__restrict__ fin, const typename Ty<PREC>::S *__restrict__ gin,
         typename Ty<PREC>::S *__restrict__ fout, typename Ty<PREC>::S *__restrict__ gout,
@@ -1160,8 +1219,8 @@ k_fused(KParams kp, const typename Ty<PREC>::S *__restrict__ fin, const typename
         const typename Ty<PREC>::R *__restrict__ rprev, const typename Ty<PREC>::R *__restrict__ pprev,
         unsigned long long *__restrict__ cnt, int chunk)
 {
-    fused_tile<D, PREC, TX, TY, NTH>(kp, fin, gin, fout, gout, rho, phi, rprev, pprev, cnt, chunk, blockIdx.x,
-                                     blockIdx.y);
+    fused_tile<D, PREC, TX, TY, NTH, false, ONE>(kp, fin, gin, fout, gout, rho, phi, rprev, pprev, cnt, chunk,
+                                                 blockIdx.x, blockIdx.y);
 }
 
 template <int D, int PREC, int TX, int TY, int NTH>
@@ -1736,14 +1795,20 @@ FusedGeom fused_geometry(const KParams &kp, int prec)
     return g;
 }
 
-template <int D, int PREC, int TX, int TY, int NTH>
+// ONE_OK: a one-plane instantiation exists and is taken when the chunk is 1
+template <int D, int PREC, int TX, int TY, int NTH, bool ONE_OK = false>
 static int fused_t(const KParams &kp, const Buffers &b, int pc, int fc, hipStream_t st)
 {
     FusedGeom g = fused_geometry(kp, PREC);
     dim3 grid((unsigned)g.ntiles, (unsigned)g.nchunks);
-    stage_launch(k_fused<D, PREC, TX, TY, NTH>, grid, dim3(NTH), st, true, true, kp, (SP<PREC>)b.f[pc],
-                 (SP<PREC>)b.g[pc], (SP<PREC>)b.f[1 - pc], (SP<PREC>)b.g[1 - pc], (RP<PREC>)b.rho[1 - fc],
-                 (RP<PREC>)b.phi[1 - fc], (RP<PREC>)b.rho[fc], (RP<PREC>)b.phi[fc], b.counters, g.chunk);
+    if (ONE_OK && g.chunk == 1)
+        stage_launch(k_fused<D, PREC, TX, TY, NTH, ONE_OK>, grid, dim3(NTH), st, true, true, kp, (SP<PREC>)b.f[pc],
+                     (SP<PREC>)b.g[pc], (SP<PREC>)b.f[1 - pc], (SP<PREC>)b.g[1 - pc], (RP<PREC>)b.rho[1 - fc],
+                     (RP<PREC>)b.phi[1 - fc], (RP<PREC>)b.rho[fc], (RP<PREC>)b.phi[fc], b.counters, g.chunk);
+    else
+        stage_launch(k_fused<D, PREC, TX, TY, NTH>, grid, dim3(NTH), st, true, true, kp, (SP<PREC>)b.f[pc],
+                     (SP<PREC>)b.g[pc], (SP<PREC>)b.f[1 - pc], (SP<PREC>)b.g[1 - pc], (RP<PREC>)b.rho[1 - fc],
+                     (RP<PREC>)b.phi[1 - fc], (RP<PREC>)b.rho[fc], (RP<PREC>)b.phi[fc], b.counters, g.chunk);
     return LBM3_CHECK_LAUNCH();
 }
 
@@ -1772,9 +1837,9 @@ int launch_fused(const KParams &kp, int prec, const Buffers &b, int pc, int fc, 
     hipStream_t st = (hipStream_t)stream;
     const int cls = fused_class(kp);
     if (cls == 0) {
-        if (prec == P64) return fused_t<2, P64, 62, 1, 64>(kp, b, pc, fc, st);
-        if (prec == P32) return fused_t<2, P32, 62, 1, 64>(kp, b, pc, fc, st);
-        return fused_t<2, P16, 62, 1, 64>(kp, b, pc, fc, st);
+        if (prec == P64) return fused_t<2, P64, 62, 1, 64, true>(kp, b, pc, fc, st);
+        if (prec == P32) return fused_t<2, P32, 62, 1, 64, true>(kp, b, pc, fc, st);
+        return fused_t<2, P16, 62, 1, 64, true>(kp, b, pc, fc, st);
     }
     if (cls == 1) {
         if (prec == P64) return fused_t<2, P64, 254, 1, 256>(kp, b, pc, fc, st);
