@@ -86,6 +86,14 @@ bool validate(const lbm3_params *p, std::string &why)
     return true;
 }
 
+// the alpha-statistics slots: kCntSlots shared ones, then one per block of
+// the small 2D fused kernel
+size_t counter_slots(const lbm3_params *p)
+{
+    const int D = lattice_D(p->lattice);
+    return (size_t)lbm3k::kCntSlots + (size_t)lbm3k::small2d_block_slots(D, p->n[0], p->n[D - 1]);
+}
+
 Layout layout(const lbm3_params *p)
 {
     Layout L{};
@@ -102,7 +110,7 @@ Layout layout(const lbm3_params *p)
     for (int k = 0; k < 2; ++k) L.phi[k] = take((size_t)N * r);
     L.fmu = D == 3 ? take((size_t)(D + 1) * N * r) : 0;  // F, mu_phi of the two-kernel step
     L.scratch = take((size_t)N * 8);
-    L.counters = take((size_t)lbm3k::kCntSlots * lbm3k::kCntStride * sizeof(unsigned long long));
+    L.counters = take(counter_slots(p) * lbm3k::kCntStride * sizeof(unsigned long long));
     L.partials = take((size_t)1024 * 16 * sizeof(double));
     L.result = take(32 * sizeof(double));
     L.total = off;
@@ -266,7 +274,7 @@ lbm3_status lbm3_init(lbm3 *h, const double *rho0, const double *phi0)
     }
     if (lbm3k::launch_ghost(k, h->prec, h->b, 0, h->stream)) return set_err(h, LBM3_EDEVICE, "ghost launch failed");
     if (lbm3k::launch_init(k, h->prec, h->b, h->stream)) return set_err(h, LBM3_EDEVICE, "init launch failed");
-    if ((e = hipMemsetAsync(h->b.counters, 0, (size_t)lbm3k::kCntSlots * lbm3k::kCntStride * sizeof(unsigned long long),
+    if ((e = hipMemsetAsync(h->b.counters, 0, counter_slots(&h->p) * lbm3k::kCntStride * sizeof(unsigned long long),
                             h->stream)) != hipSuccess)
         return hip_err(h, e, "counters");
     if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return hip_err(h, e, "init");
@@ -417,15 +425,16 @@ lbm3_status lbm3_observe(lbm3 *h, uint32_t what, lbm3_obs *out, double *rho_out,
         if (lbm3k::launch_observe(k, h->prec, h->b, h->pc, h->fc, h->stream))
             return set_err(h, LBM3_EDEVICE, "observe launch failed");
         double r[16];
-        std::vector<unsigned long long> slots((size_t)lbm3k::kCntSlots * lbm3k::kCntStride);
+        const size_t nslots = counter_slots(&h->p);
+        std::vector<unsigned long long> slots(nslots * lbm3k::kCntStride);
         if ((e = hipMemcpyAsync(r, h->b.result, sizeof(r), hipMemcpyDeviceToHost, h->stream)) != hipSuccess ||
             (e = hipMemcpyAsync(slots.data(), h->b.counters, slots.size() * sizeof(unsigned long long),
                                 hipMemcpyDeviceToHost, h->stream)) != hipSuccess)
             return hip_err(h, e, "observe download");
         if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return hip_err(h, e, "observe");
         unsigned long long c[3] = {0, 0, 0};
-        for (int k = 0; k < lbm3k::kCntSlots; ++k)
-            for (int q = 0; q < 3; ++q) c[q] += slots[(size_t)k * lbm3k::kCntStride + q];
+        for (size_t k = 0; k < nslots; ++k)
+            for (int q = 0; q < 3; ++q) c[q] += slots[k * lbm3k::kCntStride + q];
         for (int q = 0; q < 3; ++q) out->mass[q] = r[q];
         out->rho_sum = r[3];
         out->phi_sum = r[4];

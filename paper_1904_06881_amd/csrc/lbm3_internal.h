@@ -30,8 +30,20 @@ constexpr unsigned kFlagFused3D = 4u;
 
 // alpha statistics: blocks add into one of kCntSlots slots (by block index),
 // each a 128-byte line, so a launch's atomics do not queue on one address;
-// the reader sums the slots
+// the reader sums the slots.  The small 2D fused kernel instead keeps one
+// slot per block after those (small2d_block_slots of them), which the block
+// owns: it reads its running counts with the fields and stores the sums at
+// its end, without atomics (whose completion held the end of every launch).
 constexpr int kCntSlots = 64, kCntStride = 16;
+// the small 2D tile class: below kSmall2DNodes nodes, tiles of kSmall2DTX
+constexpr long long kSmall2DNodes = 1LL << 20;
+constexpr int kSmall2DTX = 62;
+// per-block slots of the small 2D class for a D-dimensional nx x nw grid
+// (nw: nodes along the wall axis), 0 for the other classes
+inline long long small2d_block_slots(int D, long long nx, long long nw)
+{
+    return (D == 2 && nx * nw < kSmall2DNodes) ? ((nx + kSmall2DTX - 1) / kSmall2DTX) * nw : 0;
+}
 
 enum Prec { P64 = 0, P32 = 1, P16 = 2 };
 
@@ -41,7 +53,7 @@ struct Buffers {
     void *rho[2], *phi[2];       // fields [N], compute type
     void *fmu;                   // 3D two-kernel step: F, mu_phi [D + 1][N], compute type
     double *scratch;             // N doubles (upload / export staging)
-    unsigned long long *counters;// kCntSlots slots of kCntStride: newton, shortcut, fallback
+    unsigned long long *counters;// kCntSlots (+ per-block) slots of kCntStride: newton, shortcut, fallback
     double *partials;            // reduction partials
     double *result;              // 32 doubles of reduced observables
     int n_partials;              // capacity in blocks

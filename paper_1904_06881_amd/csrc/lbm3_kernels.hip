@@ -1068,6 +1068,12 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
     };
     // alpha kinds of the wave's nodes, counted per plane with ballots
     unsigned long long wave_cnt[3] = {0, 0, 0};
+    // small 2D class: the block's own running counts (every lane loads, so
+    // the load is not under a branch), stored back at the end
+    constexpr bool OWNSLOT = D == 2 && NTH <= 64 && !SPLIT;
+    unsigned long long *const bslot = cnt + (size_t)(kCntSlots + by * ntx + bx) * kCntStride;
+    unsigned long long run_cnt = 0;
+    if constexpr (OWNSLOT) run_cnt = bslot[tid < 3 ? tid : 2];
 
     if (ONE) pe = pb + 1;
     for (int p = pb; p < pe; ++p) {
@@ -1203,9 +1209,11 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
     }
     if constexpr (SPLIT) return;
     // alpha statistics: one add per wave and kind (a one-wave block adds to
-    // its counter slot directly)
+    // its counter slot directly; the small 2D class stores its own slot)
     unsigned long long *slot = cnt + (size_t)((bx + by * 7) & (kCntSlots - 1)) * kCntStride;
-    if constexpr (NTH <= 64) {
+    if constexpr (OWNSLOT) {
+        if (tid < 3) bslot[tid] = run_cnt + wave_cnt[tid == 0 ? 0 : (tid == 1 ? 1 : 2)];
+    } else if constexpr (NTH <= 64) {
         if (tid < 3 && wave_cnt[tid == 0 ? 0 : (tid == 1 ? 1 : 2)])
             atomicAdd(&slot[tid], wave_cnt[tid == 0 ? 0 : (tid == 1 ? 1 : 2)]);
     } else {
@@ -1760,12 +1768,13 @@ int launch_ghost(const KParams &kp, int prec, const Buffers &b, int fdst, void *
 // chunk of march planes per block: about `target` blocks.  Measured per tile
 // class: the small 2D tiles (one wave each, all resident at once) run best
 // with one plane per block up to 8192 blocks (2048 x 64: 9 % faster than two
-// planes); the 254-node 2D tiles with one round of resident blocks (4 per
-// CU) and at least two planes, so the ring prologue is amortised; the 3D
-// tiles with 8-plane chunks on a 256^3 grid.
+// planes); the 254-node 2D tiles with about 2048 blocks and at least two
+// planes, so the ring prologue is amortised (4096 x 256: three-plane chunks
+// 1.3 % faster than five, two-plane ones 2 % slower); the 3D tiles with
+// 8-plane chunks on a 256^3 grid.
 static int choose_chunk(int cls, long long tiles, int planes)
 {
-    const long long target = cls == 0 ? 8192 : (cls == 1 ? 1024 : 4096);
+    const long long target = cls == 0 ? 8192 : (cls == 1 ? 2048 : 4096);
     const long long cmin = cls == 0 ? 1 : 2;
     long long c = (tiles * planes + target - 1) / target;
     if (c < cmin) c = cmin;
@@ -1776,7 +1785,7 @@ static int choose_chunk(int cls, long long tiles, int planes)
 
 static void tile_of_class(int cls, int prec, int &TX, int &TY)
 {
-    if (cls == 0) { TX = 62; TY = 1; }
+    if (cls == 0) { TX = kSmall2DTX; TY = 1; }
     else if (cls == 1) { TX = 254; TY = 1; }
     else if (cls == 2) { TX = 32; TY = prec == P64 ? 4 : 16; }
     else { TX = 32; TY = prec == P64 ? 4 : 8; }  // stencil pass: two blocks per CU
@@ -1786,7 +1795,7 @@ static void tile_of_class(int cls, int prec, int &TX, int &TY)
 static int fused_class(const KParams &kp)
 {
     if (kp.D == 3) return (kp.flags & kFlagFused3D) ? 2 : 3;
-    return (long long)kp.nx * kp.nw < (1LL << 20) ? 0 : 1;
+    return (long long)kp.nx * kp.nw < kSmall2DNodes ? 0 : 1;
 }
 
 bool two_kernel_step(const KParams &kp) { return fused_class(kp) == 3; }
