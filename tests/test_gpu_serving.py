@@ -42,11 +42,14 @@ def mixed_cases():
     ]
 
 
-def alone(p, init, nsteps):
+def alone(p, init, nsteps, counts=None):
     s = L.Sim(p)
     s.init(*init)
     s.step(nsteps)
     out = s.fields() + s.pops()
+    if counts is not None:
+        o = s.observe()
+        counts.extend(o[k] for k in ("n_newton", "n_shortcut", "n_fallback"))
     s.close()
     return out
 
@@ -67,11 +70,16 @@ def test_batched_steps_equal_steps_alone():
     del ws1, ws2
     for k, (p, init) in enumerate(cases):
         say("compare", k)
-        ref = alone(p, init, 31)
+        cref = []
+        ref = alone(p, init, 31, cref)
         got = sims[k].fields() + sims[k].pops()
         for a, b in zip(ref, got):
             assert np.array_equal(a, b), k
-        assert sims[k].observe()["step"] == 31
+        o = sims[k].observe()
+        assert o["step"] == 31
+        # the entropic-alpha statistics, counted in the batched kernels'
+        # own slots, equal those of the run alone
+        assert [o[q] for q in ("n_newton", "n_shortcut", "n_fallback")] == cref, k
         sims[k].close()
 
 
