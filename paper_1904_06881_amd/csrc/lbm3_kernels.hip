@@ -1071,7 +1071,7 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
     // small 2D class: the block's own running counts (every lane loads, so
     // the load is not under a branch), stored back at the end
     constexpr bool OWNSLOT = D == 2 && NTH <= 64 && !SPLIT;
-    unsigned long long *const bslot = cnt + (size_t)(kCntSlots + by * ntx + bx) * kCntStride;
+    unsigned long long *const bslot = OWNSLOT ? cnt + (size_t)(kCntSlots + by * ntx + bx) * kCntStride : nullptr;
     unsigned long long run_cnt = 0;
     if constexpr (OWNSLOT) run_cnt = bslot[tid < 3 ? tid : 2];
 
