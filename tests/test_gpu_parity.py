@@ -105,12 +105,14 @@ def test_fp64_2000_steps_cfg1():
         assert abs(og[key] - oo[key]) <= max(2, 1e-5 * oo[key]), (key, og[key], oo[key])
 
 
-@pytest.mark.parametrize("case", ["force", "extrap", "periodic", "ragged", "asym_random", "high_wall"])
+@pytest.mark.parametrize("case", ["force", "extrap", "periodic", "ragged", "asym_random", "high_wall",
+                                  "steep_random"])
 def test_fp64_variants(case):
     """FP64 parity over 40 steps on the other code paths: force method with
     wall forces, geometric extrapolation, fully periodic, a ragged grid, three
     components with kappa2 != kappa3 on random fields, angles that differ per
-    wall and interface."""
+    wall and interface, and steep angles whose interpolation points lie beyond
+    the LDS halo (read from the fields in memory)."""
     steps = 40
     if case == "force":
         rho0, phi0 = I.sessile_drop_2d(64, 40, 12, xc=32)
@@ -126,6 +128,12 @@ def test_fp64_variants(case):
     elif case == "ragged":
         rho0, phi0 = I.sessile_drop_2d(77, 23, 8, xc=30)
         p = L.make_params(L.D2Q9, (77, 23), gamma=(0.01, 0.01, 0.01), width=4.0, theta_deg=110.0)
+    elif case == "steep_random":
+        # contact angles with |cot| up to 2.9: interpolation points up to
+        # three nodes along the wall, beyond the tile's LDS halo at its edges
+        rho0, phi0 = I.random_fields((30, 70), seed=23)
+        p = L.make_params(L.D2Q9, (70, 30), gamma=(0.01, 0.01, 0.01), width=4.0,
+                          theta_deg=[[20, 160, 25], [155, 22, 158]])
     elif case == "asym_random":
         rho0, phi0 = I.random_fields((30, 50), seed=11)
         p = L.make_params(L.D2Q9, (50, 30), lam=(0.07, 0.04, 0.02), kap=(0.03, 0.05, 0.012),
