@@ -210,8 +210,10 @@ lbm3_status lbm3_step_batch(lbm3 *const *hs, int32_t n, int64_t nsteps, void *st
  * rounds, so small grids are not held to the step time of large ones and the
  * lanes overlap on the GPU.  A lane's round retires its finished
  * simulations, admits queued ones of its size first-come first-served while
- * their device footprint fits the shared pool (later requests may pass one
- * that does not fit, until it has waited max_skips rounds) and enqueues up
+ * their device footprint fits the shared pool and, in the large lane, while
+ * the lane holds at most 2^23 nodes (one grid is always admitted; larger
+ * grids fill the GPU alone) -- later requests may pass one that does not
+ * fit, until it has waited max_skips rounds -- and enqueues up
  * to `quantum` batched steps of everything resident in it.  Tension
  * calibration (lbm3_resolve) runs at submission, on the host. */
 typedef struct lbm3_server lbm3_server;
