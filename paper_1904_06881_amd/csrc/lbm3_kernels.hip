@@ -1728,9 +1728,14 @@ static void stage_launch(F kernel, dim3 grid, dim3 block, hipStream_t st, bool f
 }
 
 template <int D, int PREC>
+// 2D: blocks of 64 threads (four per 256-thread block of moments_blocks), so
+// that a small grid's few thousand threads spread over more CUs (2048 x 64:
+// step 1.7 % faster); the batched launch keeps 256
 static int moments_t(const KParams &kp, const Buffers &b, int pc, int fc, hipStream_t st)
 {
-    stage_launch(k_moments<D, PREC>, dim3((unsigned)moments_blocks(kp, PREC)), dim3(256), st, true, true, kp,
+    constexpr unsigned split = D == 2 ? 4u : 1u;
+    stage_launch(k_moments<D, PREC>, dim3((unsigned)moments_blocks(kp, PREC) * split), dim3(256 / split), st, true,
+                 true, kp,
                  (SP<PREC>)b.f[pc], (SP<PREC>)b.g[pc], (RP<PREC>)b.rho[fc], (RP<PREC>)b.phi[fc],
                  (RP<PREC>)b.rho[1 - fc], (RP<PREC>)b.phi[1 - fc]);
     return LBM3_CHECK_LAUNCH();
