@@ -153,7 +153,7 @@ __device__ __forceinline__ void bulk(const Thermo<R> &t, R rho, R phi, R &mrb, R
     R C3 = (R)0.5 * ((R)1 - ph - C1);
     R br = t.b * rho;
     R d = br - (R)4;
-    R id = (R)1 / d;
+    R id = fdiv((R)1, d);
     R lr = flog(rho);
     R dpsi = t.C - (R)2 * t.a * rho + t.T * ((R)1 + lr) + (R)16 * t.T * (br - (R)12) * id * id * id;
     R psi = rho * (t.C - t.a * rho - (R)8 * t.T * (br - (R)6) * id * id + t.T * lr);
@@ -272,9 +272,9 @@ __device__ __forceinline__ R entropic_alpha(const R *fp, R *dx, R eps, R tol, in
         S4 += fp[i] * x2 * x2;
     }
     // min over x < 0 of -1/x is -1/min(x) (the division is monotone)
-    const R amax = xmin < (R)0 ? (R)-1 / xmin : (R)INFINITY;
+    const R amax = xmin < (R)0 ? fdiv((R)-1, xmin) : (R)INFINITY;
     const R den = (R)3 * S2 - (R)4 * S3;
-    const R as = den > (R)0 ? (R)2 + (S3 - (R)2 * S4) / den : (R)2;
+    const R as = den > (R)0 ? (R)2 + fdiv(S3 - (R)2 * S4, den) : (R)2;
     if (xmax < eps) { kind = 0; return as; }
     R K = 0;
 #pragma unroll
@@ -296,7 +296,7 @@ __device__ __forceinline__ R entropic_alpha(const R *fp, R *dx, R eps, R tol, in
         G -= al * K;
         G1 -= K;
         if (!(G1 > (R)0)) break;
-        R an = al - G / G1;
+        R an = al - fdiv(G, G1);
         if (an >= amax) an = (R)0.5 * (al + amax);
         if (an <= (R)1) an = (R)0.5 * (al + (R)1);
         const R st = fabs(an - al);
@@ -1150,7 +1150,7 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
                         if (cdir(D, i, a) != 0) j[a] += (R)cdir(D, i, a) * f[i];
                 }
                 R u[3], du[3], v[3];
-                const R ir = (R)1 / r0;
+                const R ir = fdiv((R)1, r0);
 #pragma unroll
                 for (int a = 0; a < D; ++a) {
                     u[a] = j[a] * ir;
@@ -1351,7 +1351,7 @@ __device__ __forceinline__ int collide_node(const KParams &kp, const typename Ty
             if (cdir(D, i, a) != 0) j[a] += (R)cdir(D, i, a) * f[i];
     }
     R u[3], du[3], v[3];
-    const R ir = (R)1 / r0;
+    const R ir = fdiv((R)1, r0);
 #pragma unroll
     for (int a = 0; a < D; ++a) {
         u[a] = j[a] * ir;
