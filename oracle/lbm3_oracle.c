@@ -723,10 +723,13 @@ static void pass_thermo(or_state *s)
  * B(U)^2 = rho_y/rho_x (B of Eq. 27), for any alpha and beta.  The plain
  * isotropic stencil of rho/3 lets the soft gas phase run away at large
  * density ratios.
- * reading of the wall rule (Sec. IV): on the first fluid layer every
- * derivative normal to the wall is dropped; the in-layer derivatives of P are
- * central differences within the layer and the ideal part uses the in-layer
- * axis links, sum_b [Pi(x, x + e_b) - Pi(x, x - e_b)] e_b.
+ * reading of the wall rule (Sec. IV): on the first fluid layer the pressure
+ * tensor, which is not defined on the solid nodes, has its wall-normal
+ * derivatives dropped and its in-layer derivatives taken as central
+ * differences within the layer; the ideal part needs only rho, which the
+ * ghost nodes hold, and uses the axis links including the wall-normal one,
+ * sum_b [Pi(x, x + e_b) - Pi(x, x - e_b)] e_b (the wetting ghost values so
+ * enter the momentum balance of the contact line).
  * Force method (Eq. 43): on the second fluid layer
  *   F_s = rho_rel (kw_rho + phi_rel kw_phi) sum_i w_i s(x + 2 c_i) c_i
  *       = -(1/6) rho_rel (kw_rho + phi_rel kw_phi) n_wall,
@@ -767,6 +770,15 @@ static void pass_force(or_state *s)
                 F[b] += link_pressure(s->rho[n], s->rho[np_]) -
                         link_pressure(s->rho[n], s->rho[nm]);
             }
+            /* wall-normal link of the ideal part, across to the ghost node */
+            int cp[3] = {0, 0, 0}, cm[3] = {0, 0, 0};
+            cp[ax] = 1;
+            cm[ax] = -1;
+            int xp, yp, zp, xm, ym, zm;
+            neighbour(s, x, y, z, cp, &xp, &yp, &zp);
+            neighbour(s, x, y, z, cm, &xm, &ym, &zm);
+            F[ax] += link_pressure(s->rho[n], s->rho[idx(s, xp, yp, zp)]) -
+                     link_pressure(s->rho[n], s->rho[idx(s, xm, ym, zm)]);
         } else {
             double r0 = s->rho[n];
             for (int i = 0; i < s->Q; ++i) {

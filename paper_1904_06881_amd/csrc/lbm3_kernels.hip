@@ -1094,7 +1094,10 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
             const bool first = walls && (p == 1 || p == nw - 2);
             R F[3] = {0, 0, 0};
             if (first) {
-                // wall rule: normal derivatives dropped, in-layer differences
+                // wall rule (Sec. IV): the pressure tensor, not defined on
+                // the solid nodes, loses its wall-normal derivatives and takes
+                // in-layer central differences; the ideal part needs only rho,
+                // which the ghost layer holds, and keeps its wall-normal link
 #pragma unroll
                 for (int b = 0; b < D - 1; ++b) {
                     const int ot = b == 0 ? 1 : TW, of = b == 0 ? 1 : FW;
@@ -1106,6 +1109,10 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
                     else
                         F[b] += link_p(r0, s_r[s0][fcen + of]) - link_p(r0, s_r[s0][fcen - of]);
                 }
+                if constexpr (QR)
+                    F[WA] += link_q(q0, s_q[sp][fcen]) - link_q(q0, s_q[sm][fcen]);
+                else
+                    F[WA] += link_p(r0, s_r[sp][fcen]) - link_p(r0, s_r[sm][fcen]);
             } else {
 #pragma unroll
                 for (int i = 0; i < Q; ++i) {
