@@ -14,6 +14,11 @@
  *
  * Readings of the paper where it is silent, ambiguous or inconsistent are
  * marked "reading:" at the place they apply.
+ *
+ * Parity unpinned: the first-fluid-layer wall rule of the force (pass_force)
+ * beyond its symmetry (force method without wall force equals the geometric
+ * method at 90 degrees, bit for bit) has no independent check; the physics
+ * tests (sessile-drop contact angles) exercise it on the GPU path.
  */
 #include "lbm3_oracle.h"
 
