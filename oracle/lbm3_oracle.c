@@ -15,10 +15,10 @@
  * Readings of the paper where it is silent, ambiguous or inconsistent are
  * marked "reading:" at the place they apply.
  *
- * Parity unpinned: the first-fluid-layer wall rule of the force (pass_force)
- * beyond its symmetry (force method without wall force equals the geometric
- * method at 90 degrees, bit for bit) has no independent check; the physics
- * tests (sessile-drop contact angles) exercise it on the GPU path.
+ * The first-fluid-layer wall rule of the force (pass_force) is pinned by its
+ * symmetry (force method without wall force equals the geometric method at
+ * 90 degrees, bit for bit) and by the contact angles geometric wetting sets
+ * on liquid drops in gas (the CPU pins); nothing else pins it.
  */
 #include "lbm3_oracle.h"
 

@@ -596,3 +596,22 @@ def test_laplace_law_liquid_liquid():
     assert abs(vals[0] - vals[1]) < 0.01 * closed
     for v in vals:
         assert abs(v - closed) < 0.05 * closed
+
+
+@pytest.mark.parametrize("theta", [60.0, 120.0])
+def test_geometric_wetting_sets_liquid_gas_angle(theta):
+    """Geometric interpolation (Sec. IV B, Eq. 47) imposes the contact angle:
+    a liquid drop in gas started as a 90-degree cap on a 120 x 60 channel
+    ends within 5 degrees of theta_21 after 3000 steps (measured 61.4 and
+    123.8; the paper reports angles within 1 degree on larger drops).  This
+    pins the first-layer wall rule of the force: with the wall-normal link of
+    the ideal part dropped as well, the ghost values stayed out of the contact
+    line's momentum balance and the drops ended near 87 and 94 degrees."""
+    nx, ny, R = 120, 60, 20.0
+    po = O.make_params(2, (nx, ny), theta_deg=theta)
+    sim = O.Sim(po)
+    sim.init(*I.cap_drop_2d(nx, ny, R, 90.0))
+    sim.step(3000)
+    rho, phi = sim.fields()
+    C2 = O.concentrations(po, rho, phi)[1]
+    assert abs(O.contact_angle_2d(C2, exclude=8.0)[0] - theta) < 5.0
