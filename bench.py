@@ -1,20 +1,24 @@
 """Benchmark: one time step of the ternary wetting LBM update on one MI355X.
 
-Workload (the capillary-filling channel): D2Q9, 2048 x 64 nodes, walls at
-y = 0 and 63, liquid-2 slug on x < 256 displacing gas, liquid-3 films of 3
-rows on both walls, gamma_ij = 0.01, interface width 4, tau = 1, density
-ratio 1000, geometric-interpolation wetting at 60 degrees; FP32 arithmetic
-and storage (FP64 and FP16-offset storage timed beside it).  Inputs are
-synthetic (seeded geometry) and resident in HBM before the timed region.
+Headline workload (the lubricated sessile drop): D3Q27, 256^3 nodes, walls at
+z = 0 and 255, a liquid-2 sphere of radius 48 resting on an 8-node liquid-3
+film over the bottom wall, gas above, density ratio 1000, gamma12 = gamma13 =
+0.02, gamma23 = 0.01, interface width 4, tau = 1, geometric-interpolation
+walls at 90 degrees; FP32 arithmetic and storage.  Inputs are synthetic
+(seeded geometry) and resident in HBM before the timed region.
 
 Prints one JSON line: MLUPS over fluid nodes, the roofline of the dominant
-kernel from HIP events on the library's stream, and the CPU oracle's MLUPS on
-a bounded sample of the same workload; beside them the HBM fractions of the
-256^3 D3Q27 and 4096 x 256 D2Q9 grids, and the serving comparison.
+kernel from HIP events recorded by the kernels' own dispatch packets on the
+library's stream, the step's fraction of the algorithmic HBM roofline, and
+the CPU oracle timed on the host on a bounded sample of the same workload;
+beside them the FP16-storage and FP64 forms of the same grid, the two D2Q9
+channel workloads, and the serving comparison.
 """
 import argparse
+import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -25,66 +29,79 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS and % HBM roofline per step; serving p50/p99 time-to-result vs plain"
 HBM_PEAK_GBS = 8000.0
-NX, NY = 2048, 64
-X_FRONT, FILM, THETA = 256, 3, 60.0
-
-
-def workload_params(L, precision):
-    return L.make_params(L.D2Q9, (NX, NY), gamma=(0.01, 0.01, 0.01), width=4.0, tau_f=1.0, tau_g=1.0,
-                         wetting=L.WET_GEOM_INTERP, theta_deg=THETA, precision=precision)
-
-
-SAMPLE_EVERY = 25  # events around the launches of every 25th step
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_fused_d2q9_2048x64.md")
+N3 = (256, 256, 256)
+GAMMA3 = (0.02, 0.02, 0.01)
+R_DROP, FILM = 48, 8
+SAMPLE_EVERY = 10   # HIP events on the launches of every 10th timed step
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1904_06881_amd", "csrc", "lbm3_kernels.hip")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "d3q27_256cube_counters.md")
 
 
-def measured_traffic(summary=PMC_SUMMARY, prefix="traffic"):
-    """HBM bytes per launch (per fused pass in the 3D two-kernel step) from a
-    committed rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE per
-    dispatch, scaled by the copy calibration), or None when the kernel
-    source has changed since the counters were taken."""
-    import hashlib
+def params3(L, precision, n=N3):
+    return L.make_params(L.D3Q27, n, gamma=GAMMA3, width=4.0, tau_f=1.0, tau_g=1.0,
+                         wetting=L.WET_GEOM_INTERP, theta_deg=90.0, precision=precision)
+
+
+def fields3(I, n=N3):
+    s = n[0] / 256.0
+    return I.lubricated_drop_3d(*n, R_DROP * s, film=max(2, int(round(FILM * s))))
+
+
+def kernel_bytes(Q, s, sf, fp16, g_read):
+    """Algorithmic HBM bytes per fluid node of each kernel of the two-kernel
+    3D step (s: population bytes, sf: field bytes):
+      moments  read both population sets, write rho, phi (FP16 storage: and
+               read the previous fields the offsets are decoded with);
+      stencil  read rho, phi, write F (3) and mu_phi;
+      collide  read f (and g unless tau_g = 1), rho, phi, F, mu_phi (FP16:
+               the previous fields), write both population sets;
+    and the step's algorithmic minimum B_alg = 4 Q s + 4 sf (read and write
+    both population sets once, write and read rho, phi once)."""
+    dec = 2 * sf if fp16 else 0
+    return {"moments": 2 * Q * s + 2 * sf + dec,
+            "stencil": 6 * sf,
+            "collide": (2 if g_read else 1) * Q * s + 2 * Q * s + 6 * sf + dec,
+            "step_alg": 4 * Q * s + 4 * sf}
+
+
+def _summary_kv(path):
+    kv = {}
     try:
-        text = open(summary).read()
+        text = open(path).read()
+    except OSError:
+        return kv
+    for line in text.splitlines():
+        if ":" in line and not line.startswith((" ", "|", "#", "`")):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    return kv
+
+
+def measured_traffic(kernel, precision):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE per dispatch, scaled by what the same
+    counters read for a plain device copy), or None when the kernel source
+    has changed since the counters were taken."""
+    kv = _summary_kv(PMC_SUMMARY)
+    try:
         src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
     except OSError:
         return None
-    kv = {}
-    for line in text.splitlines():
-        if ":" in line and not line.startswith(" "):
-            k, v = line.split(":", 1)
-            kv[k.strip()] = v.strip()
     if kv.get("kernel_source_sha256") != src:
         return None
+    key = "%s_%s" % (kernel, precision)
     try:
-        return 1024.0 * (float(kv[prefix + "_fetch_kib_per_dispatch"]) * float(kv["fetch_factor"]) +
-                         float(kv[prefix + "_write_kib_per_dispatch"]) * float(kv["write_factor"]))
+        return 1024.0 * (float(kv[key + "_fetch_kib"]) * float(kv["fetch_factor"]) +
+                         float(kv[key + "_write_kib"]) * float(kv["write_factor"]))
     except (KeyError, ValueError):
         return None
 
 
-def bytes_per_node(Q, s, sf, fp16, two_kernel=False):
-    """Algorithmic HBM bytes per fluid-node update.  Fused kernel: read and
-    write both population sets (4 Q s) and read rho, phi (2 s_f), plus the
-    previous step's rho, phi for FP16 decoding.  The 3D two-kernel step
-    (stencil pass + collide) adds a second read of rho, phi and the write and
-    read of F, mu_phi (4 values in FP32).  Moments kernel: read both sets
-    (2 Q s), write rho, phi (2 s_f) (+ decode fields for FP16).  The wall
-    ghost layers are left out."""
-    extra = 2 * sf if fp16 else 0
-    fused = 4 * Q * s + 2 * sf + extra + ((2 * sf + 2 * 4 * 4) if two_kernel else 0)
-    moments = 2 * Q * s + 2 * sf + extra
-    alg = 4 * Q * s + 4 * sf  # one read + one write of everything a step must touch
-    return fused, moments, alg
-
-
-def run_gpu(L, I, precision, steps, warmup):
+def run3(L, I, precision, steps, warmup, n=N3, init=None):
     import torch
-    p = workload_params(L, precision)
+    p = params3(L, precision, n)
     sim = L.Sim(p, device="cuda:0")
-    rho0, phi0 = I.capillary_2d(NX, NY, X_FRONT, film=FILM)
-    sim.init(rho0, phi0)
+    sim.init(*(init if init is not None else fields3(I, n)))
     sim.step(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -93,65 +110,47 @@ def run_gpu(L, I, precision, steps, warmup):
     wall = time.perf_counter() - t0
     obs = sim.observe()
     sim.close()
+    del sim
+    torch.cuda.empty_cache()
     return wall, prof, obs
 
 
-# Large grids: the other two stencil workloads at full size, timed with the
-# same sampled events (fused-launch HBM fraction at algorithmic bytes).
-#   D3Q27 lubricated sessile drop, 256^3, sphere r = 48 on an 8-node film,
-#   gamma (0.02, 0.02, 0.01), 90 deg walls: FP32 and FP16-offset storage;
-#   D2Q9 drop train, 4096 x 256, 16 alternating drops r = 40 spaced 200,
-#   theta (45, 120, 90) deg: FP32.
-LARGE = (
-    ("d3q27_256cube_fp32", "D3Q27", (256, 256, 256), "fp32", 20, 5),
-    ("d3q27_256cube_fp16s", "D3Q27", (256, 256, 256), "fp16s", 20, 5),
-    ("d2q9_4096x256_fp32", "D2Q9", (4096, 256), "fp32", 400, 100),
-)
-# counter summaries of the same runs: (file, key prefix) per grid
-LARGE_PMC = {
-    "d3q27_256cube_fp32": (os.path.join(ROOT, "profiles", "k_collide_d3q27_256cube.md"), "traffic_fp32"),
-    "d3q27_256cube_fp16s": (os.path.join(ROOT, "profiles", "k_collide_d3q27_256cube.md"), "traffic_fp16s"),
-    "d2q9_4096x256_fp32": (os.path.join(ROOT, "profiles", "k_fused_d2q9_4096x256.md"), "traffic"),
-}
-
-
-def large_grids(L, I):
+# Other workloads, timed the same way: the two D2Q9 channels.
+#   capillary channel 2048 x 64: liquid-2 slug x < 256, liquid-3 films of 3
+#     rows, theta 60 deg (state 21 MB: resident in the 256 MB Infinity Cache,
+#     so no HBM fraction is quoted for it);
+#   drop train 4096 x 256: 16 alternating drops r = 40 spaced 200 (PCG64
+#     seed 0 jitter), theta (45, 120, 90) deg.
+def other_grids(L, I):
     import torch
     out = {}
-    init3 = None
-    for name, lat, n, prec, steps, warm in LARGE:
-        P = {"fp32": L.FP32, "fp16s": L.FP16S}[prec]
-        if lat == "D3Q27":
-            p = L.make_params(L.D3Q27, n, gamma=(0.02, 0.02, 0.01), width=4.0, theta_deg=90.0, precision=P)
-            if init3 is None:
-                init3 = I.lubricated_drop_3d(*n, 48, film=8)
-            init, Q, fluid = init3, 27, n[0] * n[1] * (n[2] - 2)
-        else:
-            p = L.make_params(L.D2Q9, n, gamma=(0.01, 0.01, 0.01), width=4.0, theta_deg=(45.0, 120.0, 90.0),
-                              precision=P)
-            init, Q, fluid = I.drop_train_2d(*n), 9, n[0] * (n[1] - 2)
+    cases = (
+        ("d2q9_2048x64_capillary_fp32", (2048, 64), 60.0, lambda: I.capillary_2d(2048, 64, 256, film=3), 2000, 200,
+         False),
+        ("d2q9_4096x256_drop_train_fp32", (4096, 256), (45.0, 120.0, 90.0), lambda: I.drop_train_2d(4096, 256),
+         400, 50, True),
+    )
+    for name, n, th, mk, steps, warm, hbm in cases:
+        p = L.make_params(L.D2Q9, n, gamma=(0.01, 0.01, 0.01), width=4.0, theta_deg=th, precision=L.FP32)
         s = L.Sim(p, device="cuda:0")
-        s.init(*init)
+        s.init(*mk())
         s.step(warm)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        pr = s.step_profiled(steps, 5)
+        pr = s.step_profiled(steps, SAMPLE_EVERY)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         o = s.observe()
         s.close()
         del s
         torch.cuda.empty_cache()
-        fb, mb, ab = bytes_per_node(Q, 2 if prec == "fp16s" else 4, 4, prec == "fp16s", two_kernel=Q == 27)
-        fgbs = fb * fluid / (pr["fused"] * 1e-3) / 1e9
-        mgbs = mb * fluid / (pr["moments"] * 1e-3) / 1e9
-        out[name] = {"MLUPS": fluid * steps / wall / 1e6, "ms_per_step": 1e3 * wall / steps,
-                     "fused_ms": pr["fused"], "fused_GBs": fgbs, "fused_frac": fgbs / HBM_PEAK_GBS,
-                     "moments_ms": pr["moments"], "moments_GBs": mgbs, "moments_frac": mgbs / HBM_PEAK_GBS,
-                     "bytes_per_node": {"fused": fb, "moments": mb, "step_min": ab},
-                     "step_frac": fluid * steps / wall * ab / (HBM_PEAK_GBS * 1e9),
-                     "fused_traffic": measured_traffic(*LARGE_PMC[name]),
-                     "n_bad": o["n_bad"]}
+        fluid = n[0] * (n[1] - 2)
+        rec = {"MLUPS": fluid * steps / wall / 1e6, "ms_per_step": 1e3 * wall / steps,
+               "moments_ms": pr["moments"], "fused_ms": pr["fused"], "steps": steps, "n_bad": o["n_bad"]}
+        if hbm:
+            alg = 4 * 9 * 4 + 4 * 4
+            rec["step_frac_alg"] = fluid * steps / wall * alg / (HBM_PEAK_GBS * 1e9)
+        out[name] = rec
     return out
 
 
@@ -259,46 +258,69 @@ def serving_leg(L, I):
     return out
 
 
-def cpu_baseline(target_s=12.0):
-    import numpy as np
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline():
+    """The FP64 CPU oracle on the host: all threads on 2 steps of the full
+    256^3 workload, and one thread on 1 step of a 96^3 grid of the same
+    recipe (sphere and film scaled), each after its own initialisation."""
     from oracle import oracle as O
     from paper_1904_06881_amd import inputs as I
     from paper_1904_06881_amd import lbm3 as L
-    d = L.lbm3_resolve(workload_params(L, L.FP64))
-    eos = {k: getattr(d, k) for k in ("a", "b", "T", "C", "psi0", "rho_l", "rho_g")}
-    po = O.make_params(2, (NX, NY), lam=list(d.lam), kap=list(d.kap), theta_deg=THETA, eos=eos,
-                       rho_l=d.rho_l, rho_g=d.rho_g)
-    sim = O.Sim(po)
-    rho0, phi0 = I.capillary_2d(NX, NY, X_FRONT, film=FILM)
-    sim.init(rho0, phi0)
-    t0 = time.perf_counter()
-    sim.step(5)
-    t5 = time.perf_counter() - t0
-    n = max(10, int(target_s / max(t5 / 5, 1e-6)))
-    t0 = time.perf_counter()
-    sim.step(n)
-    dt = time.perf_counter() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    fluid = NX * (NY - 2)
-    return {"value": fluid * n / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
-            "sample": "%d steps of the same 2048x64 FP64 workload after 5 warm-up steps (%.1f s)" % (n, dt)}
+
+    def time_oracle(n, steps):
+        d = L.lbm3_resolve(params3(L, L.FP64, n))
+        eos = {k: getattr(d, k) for k in ("a", "b", "T", "C", "psi0", "rho_l", "rho_g")}
+        po = O.make_params(3, n, lam=list(d.lam), kap=list(d.kap), theta_deg=90.0, eos=eos,
+                           rho_l=d.rho_l, rho_g=d.rho_g)
+        sim = O.Sim(po)
+        sim.init(*fields3(I, n))
+        t0 = time.perf_counter()
+        sim.step(steps)
+        dt = time.perf_counter() - t0
+        del sim
+        fluid = n[0] * n[1] * (n[2] - 2)
+        return fluid * steps / dt / 1e6, dt
+
+    threads = O.get_threads()
+    v_all, dt_all = time_oracle(N3, 2)
+    O.set_threads(1)
+    n1 = (96, 96, 96)
+    v_one, dt_one = time_oracle(n1, 1)
+    O.set_threads(threads)
+    return {"value": v_all, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": "2 steps of the 256^3 FP64 workload after initialisation (%.1f s)" % dt_all,
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "one_core": {"value": v_one, "unit": "MLUPS", "cores": 1,
+                         "sample": "1 step of a 96^3 grid of the same recipe (sphere r 18, film 3; %.1f s)"
+                                   % dt_one}}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5000)
-    ap.add_argument("--warmup", type=int, default=500)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-variants", action="store_true", help="skip the FP64 / FP16-storage runs")
+    ap.add_argument("--no-variants", action="store_true", help="skip the FP16-storage and FP64 forms")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving comparison")
-    ap.add_argument("--no-large", action="store_true", help="skip the 256^3 and 4096x256 grids")
+    ap.add_argument("--no-other", action="store_true", help="skip the D2Q9 channel workloads")
+    ap.add_argument("--precision", default="fp32", choices=("fp32", "fp16s", "fp64"),
+                    help="storage of the timed run (the headline is fp32)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 256 MiB device copy (HBM counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: the build runs a single simulation per device "
-              "(--gpus %d not supported)" % args.gpus, file=sys.stderr)
+        print("bench.py measures one GPU: this build runs each simulation on a single device "
+              "(--gpus %d is not supported)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -316,49 +338,63 @@ def main():
         print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4}), flush=True)
         return
 
-    fluid = NX * (NY - 2)
-    wall, prof, obs = run_gpu(L, I, L.FP32, args.steps, args.warmup)
+    precs = {"fp32": (L.FP32, 4, 4, False), "fp16s": (L.FP16S, 2, 4, True), "fp64": (L.FP64, 8, 8, False)}
+    P, s, sf, fp16 = precs[args.precision]
+    fluid = N3[0] * N3[1] * (N3[2] - 2)
+    init = fields3(I)
+    wall, prof, obs = run3(L, I, P, args.steps, args.warmup, init=init)
     ms_step = 1e3 * wall / args.steps
     mlups = fluid * args.steps / wall / 1e6
 
-    fused_b, mom_b, alg_b = bytes_per_node(9, 4, 4, False)
-    kern = {k: prof[k] for k in ("moments", "fused")}  # mean ms per launch
-    dom = max(kern, key=kern.get)
-    per_launch_bytes = {"fused": fused_b * fluid, "moments": mom_b * fluid}[dom]
-    achieved = per_launch_bytes / (kern[dom] * 1e-3) / 1e9
-    roof = {"bound": "hbm", "kernel": "k_" + dom,
-            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic() if dom == "fused" else None, "bytes_per_launch": per_launch_bytes, "avg_launch_ms": kern[dom],
+    kb = kernel_bytes(27, s, sf, fp16, g_read=False)
+    kern = {"moments": prof["moments"], "stencil": prof["stencil"], "collide": prof["collide"],
+            "ghost": prof["ghost"]}
+    dom = max(("moments", "stencil", "collide"), key=lambda k: kern[k])
+    per_launch = kb[dom] * fluid
+    achieved = per_launch / (kern[dom] * 1e-3) / 1e9
+    roof = {"bound": "hbm", "kernel": "k_" + dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom, args.precision),
+            "bytes_per_node": kb[dom], "bytes_per_launch": per_launch, "avg_launch_ms": kern[dom],
             "launches_timed": prof["sampled"]}
+    step_frac = mlups * 1e6 * kb["step_alg"] / (HBM_PEAK_GBS * 1e9)
 
     variants = {}
-    for name, prec, b in () if args.no_variants else (("f64", L.FP64, bytes_per_node(9, 8, 8, False)),
-                                                      ("f16s", L.FP16S, bytes_per_node(9, 2, 4, True))):
-        n = max(200, args.steps // 4)
-        w, pr, o = run_gpu(L, I, prec, n, min(args.warmup, 200))
-        variants[name] = {"MLUPS": fluid * n / w / 1e6, "fused_ms": pr["fused"],
-                          "fused_GBs": b[0] * fluid / (pr["fused"] * 1e-3) / 1e9,
-                          "n_bad": o["n_bad"], "alpha_fallback": o["n_fallback"]}
+    if not args.no_variants:
+        for name in ("fp16s", "fp64"):
+            if name == args.precision:
+                continue
+            Pv, sv, sfv, f16v = precs[name]
+            n = 50 if name == "fp16s" else 20
+            w, pr, o = run3(L, I, Pv, n, 5, init=init)
+            kv = kernel_bytes(27, sv, sfv, f16v, g_read=False)
+            mv = fluid * n / w / 1e6
+            variants[name] = {"MLUPS": mv, "ms_per_step": 1e3 * w / n, "moments_ms": pr["moments"],
+                              "stencil_ms": pr["stencil"], "collide_ms": pr["collide"],
+                              "step_frac_alg": mv * 1e6 * kv["step_alg"] / (HBM_PEAK_GBS * 1e9),
+                              "bytes_per_node_alg": kv["step_alg"], "n_bad": o["n_bad"]}
 
     line = {
         "metric": METRIC, "value": mlups, "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "D2Q9 capillary filling 2048x64, liquid-2 slug x<256, liquid-3 films "
-                               "3 rows, density ratio 1000, gamma 0.01, width 4, tau 1, geometric "
-                               "interpolation 60 deg, FP32 storage",
-                   "grid": [NX, NY], "fluid_nodes": fluid, "precision": "fp32", "stream_launches_per_step": 2},
-        "hbm_frac_of_step": mlups * 1e6 * alg_b / (HBM_PEAK_GBS * 1e9),
-        "bytes_per_node_alg": alg_b,
+        "vs_baseline": None, "dtype": {"fp32": "f32", "fp16s": "f32", "fp64": "f64"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": "D3Q27 lubricated sessile drop 256^3: liquid-2 sphere r 48 on an 8-node liquid-3 "
+                               "film, gas above, density ratio 1000, gamma 0.02/0.02/0.01, width 4, tau 1, "
+                               "geometric interpolation 90 deg walls at z = 0, 255; %s storage" % args.precision,
+                   "grid": list(N3), "fluid_nodes": fluid, "precision": args.precision,
+                   "kernels_per_step": 4},
+        "roofline": roof,
+        "step_roofline": {"bytes_per_node_alg": kb["step_alg"], "achieved": mlups * kb["step_alg"] / 1e3,
+                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": step_frac},
         "kernel_ms_per_launch": kern,
+        "kernel_bytes_per_node": kb,
         "n_bad": obs["n_bad"],
         "alpha_kinds": {"newton": obs["n_newton"], "small_deviation": obs["n_shortcut"],
                         "fallback": obs["n_fallback"]},
         "variants": variants,
-        "roofline": roof,
     }
-    if not args.no_large:
-        line["large_grids"] = large_grids(L, I)
+    if not args.no_other:
+        line["other_grids"] = other_grids(L, I)
     if not args.no_serving:
         line["serving"] = serving_leg(L, I)
     if not args.no_cpu:

@@ -72,7 +72,8 @@ enum {
 typedef struct {
     int32_t lattice;        /* LBM3_D2Q9 or LBM3_D3Q27 */
     int32_t n[3];           /* nx, ny, nz (nz = 1 for D2Q9); >= 3 on the wall axis;
-                               nx ny nz < 2^32 (else LBM3_EINVAL) */
+                               nx ny nz times 8 bytes (FP64) or 4 bytes (FP32,
+                               FP16S) below 4 GiB, else LBM3_EINVAL */
     int32_t walls;          /* 1: walls at both ends of the last axis; 0: periodic */
     double  rho_l, rho_g;   /* coexistence densities (Carnahan-Starling, Sec. II A):
                                the temperature follows from rho_l/rho_g at the
@@ -151,13 +152,16 @@ lbm3_status lbm3_step(lbm3 *h, int64_t nsteps);
 /* As lbm3_step, with HIP events recorded by the kernels of every
  * sample_every-th step (>= 1; LBM3_EINVAL otherwise) from their own dispatch
  * packets (start of a stage's first kernel, end of its last), so that no
- * marker packet enters the stream; synchronises.  kernel_ms (host, 5
+ * marker packet enters the stream; synchronises.  kernel_ms (host, 8
  * doubles, may be NULL) receives [0..2] the mean device time per step of the
  * three stages over the sampled steps: moments, ghost layers, and force +
  * collision + streaming (the fused kernel, or in 3D the stencil pass plus
- * the collide kernel); the ghost-layer entry is 0 in 2D, where the fused
- * kernel fills the ghost layers itself; [3] the time from before the first
- * to after the last step, and [4] the number of sampled steps. */
+ * the collide kernel, from the first one's start to the second one's end);
+ * the ghost-layer entry is 0 in 2D, where the fused kernel fills the ghost
+ * layers itself; [3] the time from before the first to after the last step,
+ * [4] the number of sampled steps, [5] and [6] the mean time of the stencil
+ * pass and of the collide kernel alone (3D two-kernel step; 0 otherwise),
+ * [7] 0. */
 lbm3_status lbm3_step_profiled(lbm3 *h, int64_t nsteps, int32_t sample_every, double *kernel_ms);
 
 /* Synchronise the stream and report the current state.  what: LBM3_OBS_*

@@ -24,6 +24,7 @@
 
 #include <float.h>
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -1122,3 +1123,8 @@ double or_flat_tension(const or_params *p, int pair, int n, double *width,
     free(r); free(ph); free(mr); free(mp);
     return gam;
 }
+
+/* OpenMP threads of the passes (timing only; the results do not depend on
+ * it: no pass reduces in floating point across threads). */
+void or_set_threads(int n) { if (n > 0) omp_set_num_threads(n); }
+int  or_get_threads(void) { return omp_get_max_threads(); }

@@ -134,6 +134,11 @@ int64_t   or_N(const or_state *s);
 double or_flat_tension(const or_params *p, int pair, int n, double *width,
                        double *rho_out, double *phi_out);
 
+/* --- timing ------------------------------------------------------------ */
+/* OpenMP threads used by the passes (the results do not depend on it). */
+void or_set_threads(int n);
+int  or_get_threads(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -93,10 +93,21 @@ def lib():
         L.or_Q.argtypes = [C.c_void_p]
         L.or_N.restype = C.c_int64
         L.or_N.argtypes = [C.c_void_p]
+        L.or_set_threads.argtypes = [C.c_int]
+        L.or_get_threads.restype = C.c_int
         L.or_flat_tension.restype = C.c_double
         L.or_flat_tension.argtypes = [C.POINTER(OrParams), C.c_int, C.c_int, dp, dp, dp]
         _lib = L
     return _lib
+
+
+def set_threads(n):
+    """OpenMP threads of the oracle's passes (timing only)."""
+    lib().or_set_threads(int(n))
+
+
+def get_threads():
+    return lib().or_get_threads()
 
 
 def _dp(a):

@@ -57,6 +57,11 @@ bool validate(const lbm3_params *p, std::string &why)
     if (p->walls && nw < 3) { why = "the wall axis needs at least 3 layers"; return false; }
     // node offsets inside one population array are 32-bit in the kernels
     if ((long long)p->n[0] * p->n[1] * nz >= (1LL << 32)) { why = "grid too large (2^32 nodes or more)"; return false; }
+    // and so are the byte offsets inside one population or field array
+    if ((long long)p->n[0] * p->n[1] * nz * (p->precision == LBM3_FP64 ? 8 : 4) >= (1LL << 32)) {
+        why = "grid too large (one population array of 4 GiB or more)";
+        return false;
+    }
     if (!(p->rho_l > 0.0) || !(p->rho_g > 0.0) || !(p->rho_l > p->rho_g)) {
         why = "need rho_l > rho_g > 0";
         return false;
@@ -317,45 +322,57 @@ lbm3_status lbm3_step_profiled(lbm3 *h, int64_t nsteps, int32_t sample_every, do
     if (!h->inited) return set_err(h, LBM3_ESTATE, "step before init");
     if (nsteps < 0 || sample_every < 1) return set_err(h, LBM3_EINVAL, "bad step count or sampling stride");
     // per sampled step a start and a stop event for each of the three stages,
-    // recorded by the stage's own kernels (no marker packets between them)
+    // recorded by the stage's own kernels (no marker packets between them),
+    // and in a two-kernel last stage the end of its first kernel and the
+    // start of its second
+    constexpr int PER = 8;
     const int batch = 64;  // sampled steps between host synchronisations
-    hipEvent_t ev[6 * batch], first = nullptr, last = nullptr;
+    hipEvent_t ev[PER * batch], first = nullptr, last = nullptr;
     int made = 0;
     hipError_t e = hipSuccess;
     lbm3_status st = LBM3_OK;
-    double acc[3] = {0, 0, 0}, span = 0;
+    double acc[5] = {0, 0, 0, 0, 0}, span = 0;
     int64_t sampled = 0;
     const bool no_ghost = lbm3k::fused_fills_ghost(h->kp);
-    for (; made < 6 * batch; ++made)
+    const bool split = lbm3k::two_kernel_step(h->kp);
+    for (; made < PER * batch; ++made)
         if ((e = hipEventCreate(&ev[made])) != hipSuccess) break;
     if (e == hipSuccess) e = hipEventCreate(&first);
     if (e == hipSuccess) e = hipEventCreate(&last);
     if (e == hipSuccess) e = hipEventRecord(first, h->stream);
     if (e != hipSuccess) st = hip_err(h, e, "event setup");
     int pending = 0;  // sampled steps whose events are not yet read
+    auto elapsed = [&](hipEvent_t a, hipEvent_t b, double &sum) -> bool {
+        float ms = 0;
+        if ((e = hipEventElapsedTime(&ms, a, b)) != hipSuccess) return false;
+        sum += ms;
+        return true;
+    };
     auto drain = [&]() -> bool {
         if (!pending) return true;
-        if ((e = hipEventSynchronize(ev[6 * (pending - 1) + 5])) != hipSuccess) return false;
-        for (int s = 0; s < pending; ++s)
+        if ((e = hipEventSynchronize(ev[PER * (pending - 1) + 5])) != hipSuccess) return false;
+        for (int s = 0; s < pending; ++s) {
+            hipEvent_t *E = ev + PER * s;
             for (int j = 0; j < 3; ++j) {
                 if (j == 1 && no_ghost) continue;
-                float ms = 0;
-                if ((e = hipEventElapsedTime(&ms, ev[6 * s + 2 * j], ev[6 * s + 2 * j + 1])) != hipSuccess) return false;
-                acc[j] += ms;
+                if (!elapsed(E[2 * j], E[2 * j + 1], acc[j])) return false;
             }
+            if (split && (!elapsed(E[4], E[6], acc[3]) || !elapsed(E[7], E[5], acc[4]))) return false;
+        }
         sampled += pending;
         pending = 0;
         return true;
     };
     for (int64_t t = 0; t < nsteps && st == LBM3_OK; ++t) {
         const bool timed = t % sample_every == 0;
-        hipEvent_t *E = ev + 6 * pending;
+        hipEvent_t *E = ev + PER * pending;
         int r = 0;
         for (int j = 0; j < 3 && !r; ++j) {
             if (j == 1 && no_ghost) continue;
-            if (timed) lbm3k::set_stage_events(E[2 * j], E[2 * j + 1]);
+            if (timed) lbm3k::set_stage_events(E[2 * j], E[2 * j + 1], j == 2 && split ? E[6] : nullptr,
+                                               j == 2 && split ? E[7] : nullptr);
             r = launch_step(h, j);
-            lbm3k::set_stage_events(nullptr, nullptr);
+            lbm3k::set_stage_events(nullptr, nullptr, nullptr, nullptr);
         }
         if (r) { st = set_err(h, LBM3_EDEVICE, "kernel launch failed"); break; }
         h->pc ^= 1;
@@ -378,6 +395,9 @@ lbm3_status lbm3_step_profiled(lbm3 *h, int64_t nsteps, int32_t sample_every, do
         for (int j = 0; j < 3; ++j) kernel_ms[j] = sampled ? acc[j] / (double)sampled : 0.0;
         kernel_ms[3] = span;
         kernel_ms[4] = (double)sampled;
+        kernel_ms[5] = sampled ? acc[3] / (double)sampled : 0.0;
+        kernel_ms[6] = sampled ? acc[4] / (double)sampled : 0.0;
+        kernel_ms[7] = 0.0;
     }
     return st;
 }

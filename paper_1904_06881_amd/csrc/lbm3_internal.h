@@ -85,8 +85,10 @@ int launch_ghost(const KParams &kp, int prec, const Buffers &b, int fdst, void *
 int launch_fused(const KParams &kp, int prec, const Buffers &b, int pc, int fc, void *stream);
 // events (hipEvent_t, or null) the next launch_moments / launch_ghost /
 // launch_fused stage records from its first kernel's start and its last
-// kernel's end; set by the profiled step, cleared with nulls
-void set_stage_events(void *start, void *stop);
+// kernel's end, and in a two-kernel stage also from the first kernel's end
+// (sub_stop) and the second kernel's start (sub_start); set by the profiled
+// step, cleared with nulls
+void set_stage_events(void *start, void *stop, void *sub_stop, void *sub_start);
 // true when the fused kernel fills the wall ghost layers itself (2D)
 bool fused_fills_ghost(const KParams &kp);
 // true when the step's last stage is the stencil pass plus the collide

@@ -362,17 +362,28 @@ __device__ __forceinline__ int collide_f(R *f, R r0, const R *u, const R *du, R 
         R fe[3][3], fd[3][3], dd[3][3];
 #pragma unroll
         for (int a = 0; a < D; ++a) feq_factor_steps(u[a], du[a], fe[a], fd[a], dd[a]);
+        // per population e = rho prod_a fe_a and the telescoped difference
+        // rho [dd_0 fd_1 (fd_2) + fe_0 dd_1 (fd_2) (+ fe_0 fe_1 dd_2)], from
+        // products over the leading axes shared by the populations
+        R ez[3], fz[3], dz[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            ez[k] = r0 * fe[D - 1][k];
+            fz[k] = r0 * fd[D - 1][k];
+            dz[k] = r0 * dd[D - 1][k];
+        }
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             const int kx = cdir(D, i, 0) + 1, ky = cdir(D, i, 1) + 1, kz = D == 3 ? cdir(D, i, 2) + 1 : 1;
             R e, dme;
             if constexpr (D == 3) {
-                e = r0 * fe[0][kx] * fe[1][ky] * fe[2][kz];
-                dme = r0 * (dd[0][kx] * fd[1][ky] * fd[2][kz] + fe[0][kx] * (dd[1][ky] * fd[2][kz] +
-                                                                              fe[1][ky] * dd[2][kz]));
+                const R pxy = fe[0][kx] * fe[1][ky];
+                const R xy = dd[0][kx] * fd[1][ky] + fe[0][kx] * dd[1][ky];
+                e = pxy * ez[kz];
+                dme = xy * fz[kz] + pxy * dz[kz];
             } else {
-                e = r0 * fe[0][kx] * fe[1][ky];
-                dme = r0 * (dd[0][kx] * fd[1][ky] + fe[0][kx] * dd[1][ky]);
+                e = fe[0][kx] * ez[ky];
+                dme = dd[0][kx] * fz[ky] + fe[0][kx] * dz[ky];
             }
             dl[i] = e - f[i];  // Delta
             f[i] += dme;       // mirror state f'
@@ -425,14 +436,20 @@ __device__ __forceinline__ int collide_f(R *f, R r0, const R *u, const R *du, R 
 }
 
 // LBGK of g toward g^eq(phi, v), v = u + du/2 (Eqs. 33-35); the rest
-// population takes phi minus the moving ones
-template <int D, typename R>
+// population takes phi minus the moving ones.  With tau_g = 1 the update is
+// g* = g^eq exactly (the stored g is not needed, and FRESH callers do not
+// load it); otherwise g* = g + (g^eq - g)/tau_g.  g^eq_i = w_i (a + v.c_i
+// (b + c v.c_i)) with a = 3 Gamma mu_phi - 1.5 phi |v|^2, b = 3 phi,
+// c = 4.5 phi.
+template <int D, typename R, bool FRESH = false>
 __device__ __forceinline__ void collide_g(R *gg, const R *v, R p0, R mup, R Gam, R itg)
 {
     constexpr int Q = D == 2 ? 9 : 27;
     R vv = 0;
 #pragma unroll
     for (int a = 0; a < D; ++a) vv += v[a] * v[a];
+    const R ca = (R)3 * Gam * mup - (R)1.5 * p0 * vv, cb = (R)3 * p0, cc = (R)4.5 * p0;
+    const bool one = itg == (R)1;
     R sum = 0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -441,11 +458,13 @@ __device__ __forceinline__ void collide_g(R *gg, const R *v, R p0, R mup, R Gam,
 #pragma unroll
         for (int a = 0; a < D; ++a)
             if (cdir(D, i, a) != 0) vc += (R)cdir(D, i, a) * v[a];
-        R ge = (R)wgt(D, i) * ((R)3 * Gam * mup + (R)3 * p0 * vc + (R)4.5 * p0 * vc * vc - (R)1.5 * p0 * vv);
+        const R ge = (R)wgt(D, i) * (ca + vc * (cb + cc * vc));
         sum += ge;
-        gg[i] += (ge - gg[i]) * itg;
+        if constexpr (FRESH) gg[i] = ge;
+        else gg[i] = one ? ge : gg[i] + (ge - gg[i]) * itg;
     }
-    gg[Q / 2] += ((p0 - sum) - gg[Q / 2]) * itg;
+    if constexpr (FRESH) gg[Q / 2] = p0 - sum;
+    else gg[Q / 2] = one ? p0 - sum : gg[Q / 2] + ((p0 - sum) - gg[Q / 2]) * itg;
 }
 
 // -------------------------------------------------------------- moments --
@@ -1292,6 +1311,35 @@ k_stencil_batch(const SimDesc *__restrict__ d, const int *__restrict__ sim, int 
                                            local % sd.ntiles, local / sd.ntiles, on_global<R>(d, sd.fmu));
 }
 
+// Raw buffer access to one array of n elements at a uniform base: the
+// resource (base, size) lives in scalar registers and each lane supplies a
+// 32-bit byte offset, so no 64-bit address arithmetic is spent per access;
+// accesses beyond the array read 0 and drop the store.  Every array of a
+// simulation is below 4 GiB (checked when the handle is created).
+template <typename T> __device__ __forceinline__ __amdgpu_buffer_rsrc_t arr(const T *base, unsigned n)
+{
+    return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, (int)(n * (unsigned)sizeof(T)), 0x00020000);
+}
+template <typename T> __device__ __forceinline__ T ld32(__amdgpu_buffer_rsrc_t r, unsigned byte_off)
+{
+    if constexpr (sizeof(T) == 8)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 0));
+    else if constexpr (sizeof(T) == 4)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, byte_off, 0, 0));
+}
+template <typename T> __device__ __forceinline__ void st32(__amdgpu_buffer_rsrc_t r, unsigned byte_off, T v)
+{
+    using U2 = unsigned __attribute__((ext_vector_type(2)));
+    if constexpr (sizeof(T) == 8)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, v), r, byte_off, 0, 0);
+    else if constexpr (sizeof(T) == 4)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, byte_off, 0, 0);
+    else
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, byte_off, 0, 0);
+}
+
 // Collision and push streaming of fluid node number t (counted from the
 // first fluid plane), the second kernel of the two-kernel step: F and mu_phi
 // from the stencil pass, rho, phi of the node and of its push targets (for
@@ -1299,7 +1347,15 @@ k_stencil_batch(const SimDesc *__restrict__ d, const int *__restrict__ sim, int 
 // fused kernel, one node per thread with no LDS and no barriers, so the
 // waves of a CU overlap their loads and their collisions freely.  Returns
 // the alpha kind (-1: none).
-template <int D, int PREC>
+//
+// UNI: every wave lies in one plane of the wall axis (the plane stride is a
+// multiple of 64), so the plane index is taken as wave-uniform and the
+// bounce-back choice of each population is a scalar branch.  GL: whether
+// the stored g is loaded (0 never: tau_g = 1 with collisions, where
+// g* = g^eq; 1 always; 2 decided at run time by the same rule, for the
+// batched kernel).  Target addresses are the sum of an x, a y and a plane
+// byte offset, shared by the f and g stores.
+template <int D, int PREC, bool UNI, int GL>
 __device__ __forceinline__ int collide_node(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin,
                                             const typename Ty<PREC>::S *__restrict__ gin,
                                             typename Ty<PREC>::S *__restrict__ fout,
@@ -1314,40 +1370,51 @@ __device__ __forceinline__ int collide_node(const KParams &kp, const typename Ty
     using S = typename Ty<PREC>::S;
     constexpr int Q = D == 2 ? 9 : 27;
     constexpr int WA = D - 1;
+    constexpr unsigned SS = sizeof(S), SR = sizeof(R);
     const bool walls = kp.walls != 0;
     const unsigned N = (unsigned)kp.N, PS = (unsigned)kp.PS;
     const int nx = kp.nx, ny = kp.ny, nw = kp.nw;
     const unsigned n = (unsigned)((walls ? kp.PS : 0) + t);
+    const bool collide = !(kp.flags & 1u), alpha2 = (kp.flags & 2u) != 0;
+    const R itg = (R)kp.inv_tau_g;
+    const bool need_g = GL == 1 || (GL == 2 && (!collide || itg != (R)1));
 
     S fr[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) fr[i] = fin[(size_t)i * N + n];
-    const R r0 = rho[n], p0 = phi[n];
+    for (int i = 0; i < Q; ++i) fr[i] = ld32<S>(arr(fin + (size_t)i * N, N), n * SS);
+    const R r0 = ld32<R>(arr(rho, N), n * SR), p0 = ld32<R>(arr(phi, N), n * SR);
     R F[3] = {0, 0, 0};
 #pragma unroll
-    for (int a = 0; a < D; ++a) F[a] = fmu[(size_t)a * N + n];
-    const R mup = fmu[(size_t)D * N + n];
+    for (int a = 0; a < D; ++a) F[a] = ld32<R>(arr(fmu + (size_t)a * N, N), n * SR);
+    const R mup = ld32<R>(arr(fmu + (size_t)D * N, N), n * SR);
     R rp = (R)0, pp = (R)0;
-    if constexpr (PREC == P16) { rp = rprev[n]; pp = pprev[n]; }
+    if constexpr (PREC == P16) { rp = ld32<R>(arr(rprev, N), n * SR); pp = ld32<R>(arr(pprev, N), n * SR); }
 
-    // the node's coordinates and its in-plane neighbours (periodic axes)
+    // the node's coordinates; byte offsets (storage type) of x - 1, x, x + 1,
+    // of the rows y - 1, y, y + 1 and of the planes p - 1, p, p + 1
     const int x = (int)(n % (unsigned)nx);
     const unsigned rest = n / (unsigned)nx;
     const int y = D == 3 ? (int)(rest % (unsigned)ny) : 0;
-    const int p = D == 3 ? (int)(rest / (unsigned)ny) : (int)rest;
-    const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
-    const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+    int p = D == 3 ? (int)(rest / (unsigned)ny) : (int)rest;
+    if constexpr (UNI) p = __builtin_amdgcn_readfirstlane(p);
+    const unsigned xo[3] = {(unsigned)(x == 0 ? nx - 1 : x - 1) * SS, (unsigned)x * SS,
+                            (unsigned)(x == nx - 1 ? 0 : x + 1) * SS};
+    unsigned yo[3] = {0, 0, 0};
+    if constexpr (D == 3) {
+        yo[0] = (unsigned)(y == 0 ? ny - 1 : y - 1) * (unsigned)nx * SS;
+        yo[1] = (unsigned)y * (unsigned)nx * SS;
+        yo[2] = (unsigned)(y == ny - 1 ? 0 : y + 1) * (unsigned)nx * SS;
+    }
+    const int pm = walls ? p - 1 : (p == 0 ? nw - 1 : p - 1), pq = walls ? p + 1 : (p == nw - 1 ? 0 : p + 1);
+    const unsigned zo[3] = {(unsigned)pm * PS * SS, (unsigned)p * PS * SS, (unsigned)pq * PS * SS};
+    // halfway bounce-back: the populations leaving toward a wall layer
+    const bool low = walls && p == 1, high = walls && p == nw - 2;
     auto target = [&](int i) -> unsigned {
-        const int cx = cdir(D, i, 0), cy = D == 3 ? cdir(D, i, 1) : 0;
-        unsigned v = (unsigned)(cx < 0 ? xm : (cx > 0 ? xp : x));
-        if constexpr (D == 3) v += (unsigned)nx * (unsigned)(cy < 0 ? ym : (cy > 0 ? yp : y));
-        int pt = p + cdir(D, i, WA);
-        if (!walls) pt = pt < 0 ? pt + nw : (pt >= nw ? pt - nw : pt);
-        return (unsigned)pt * PS + v;
+        return xo[cdir(D, i, 0) + 1] + yo[D == 3 ? cdir(D, i, 1) + 1 : 1] + zo[cdir(D, i, WA) + 1];
     };
+    auto bounces = [&](int i) { return (cdir(D, i, WA) < 0 && low) || (cdir(D, i, WA) > 0 && high); };
 
-    const R beta = (R)kp.beta, itg = (R)kp.inv_tau_g, Gam = (R)kp.Gamma;
-    const bool collide = !(kp.flags & 1u), alpha2 = (kp.flags & 2u) != 0;
+    const R beta = (R)kp.beta, Gam = (R)kp.Gamma;
     R f[Q];
     R j[3] = {0, 0, 0};
 #pragma unroll
@@ -1369,28 +1436,36 @@ __device__ __forceinline__ int collide_node(const KParams &kp, const typename Ty
     if (collide) kind = collide_f<D, R>(f, r0, u, du, beta, (R)kp.alpha_eps, (R)kp.alpha_tol, kp.alpha_maxit, alpha2);
     // g loads ahead of the f stores (loads and stores retire in order)
     R gg[Q];
+    if constexpr (GL != 0) {
+        if (need_g) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) gg[i] = dec_g<PREC, D>(gin[(size_t)i * N + n], i, pp);
+            for (int i = 0; i < Q; ++i) gg[i] = dec_g<PREC, D>(ld32<S>(arr(gin + (size_t)i * N, N), n * SS), i, pp);
+        }
+    }
     // push streaming with halfway bounce-back at the walls
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const int pt = p + cdir(D, i, WA);
-        if (walls && (pt < 1 || pt > nw - 2)) {
-            fout[(size_t)(Q - 1 - i) * N + n] = enc_f<PREC, D>(f[i], Q - 1 - i, r0);
+        if (bounces(i)) {
+            st32<S>(arr(fout + (size_t)(Q - 1 - i) * N, N), n * SS, enc_f<PREC, D>(f[i], Q - 1 - i, r0));
         } else {
             const unsigned nt = target(i);
-            fout[(size_t)i * N + nt] = enc_f<PREC, D>(f[i], i, PREC == P16 ? rho[nt] : r0);
+            const R rt = PREC == P16 ? ld32<R>(arr(rho, N), nt / SS * SR) : r0;
+            st32<S>(arr(fout + (size_t)i * N, N), nt, enc_f<PREC, D>(f[i], i, rt));
         }
     }
-    if (collide) collide_g<D, R>(gg, v, p0, mup, Gam, itg);
+    if (!need_g) {
+        collide_g<D, R, true>(gg, v, p0, mup, Gam, itg);
+    } else if constexpr (GL != 0) {
+        if (collide) collide_g<D, R>(gg, v, p0, mup, Gam, itg);
+    }
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const int pt = p + cdir(D, i, WA);
-        if (walls && (pt < 1 || pt > nw - 2)) {
-            gout[(size_t)(Q - 1 - i) * N + n] = enc_g<PREC, D>(gg[i], Q - 1 - i, p0);
+        if (bounces(i)) {
+            st32<S>(arr(gout + (size_t)(Q - 1 - i) * N, N), n * SS, enc_g<PREC, D>(gg[i], Q - 1 - i, p0));
         } else {
             const unsigned nt = target(i);
-            gout[(size_t)i * N + nt] = enc_g<PREC, D>(gg[i], i, PREC == P16 ? phi[nt] : p0);
+            const R pt = (PREC == P16 && i == Q / 2) ? ld32<R>(arr(phi, N), nt / SS * SR) : p0;
+            st32<S>(arr(gout + (size_t)i * N, N), nt, enc_g<PREC, D>(gg[i], i, pt));
         }
     }
     return kind;
@@ -1411,7 +1486,7 @@ __device__ __forceinline__ void count_kinds(int kind, int *s_cnt)
 // 256^3 grid; four spill
 #define LBM3_COLLIDE_ATTR __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == P64 ? 1 : 3)))
 
-template <int D, int PREC>
+template <int D, int PREC, bool UNI, int GL>
 __global__ void LBM3_COLLIDE_ATTR
 k_collide(KParams kp, const typename Ty<PREC>::S *__restrict__ fin, const typename Ty<PREC>::S *__restrict__ gin,
           typename Ty<PREC>::S *__restrict__ fout, typename Ty<PREC>::S *__restrict__ gout,
@@ -1425,7 +1500,7 @@ k_collide(KParams kp, const typename Ty<PREC>::S *__restrict__ fin, const typena
     const long long count = kp.walls ? kp.N - 2 * kp.PS : kp.N;
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     int kind = -1;
-    if (t < count) kind = collide_node<D, PREC>(kp, fin, gin, fout, gout, rho, phi, rprev, pprev, fmu, t);
+    if (t < count) kind = collide_node<D, PREC, UNI, GL>(kp, fin, gin, fout, gout, rho, phi, rprev, pprev, fmu, t);
     count_kinds(kind, s_cnt);
     __syncthreads();
     if (threadIdx.x < 3 && s_cnt[threadIdx.x])
@@ -1449,11 +1524,12 @@ k_collide_batch(const SimDesc *__restrict__ d, const int *__restrict__ sim, int 
     const long long t = (long long)(blockIdx.x - sd.cblk0) * blockDim.x + threadIdx.x;
     int kind = -1;
     if (t < count)
-        kind = collide_node<D, PREC>(kp, on_global<const S>(d, sd.f[pc]), on_global<const S>(d, sd.g[pc]),
-                                     on_global<S>(d, sd.f[1 - pc]), on_global<S>(d, sd.g[1 - pc]),
-                                     on_global<const R>(d, sd.rho[1 - fc]), on_global<const R>(d, sd.phi[1 - fc]),
-                                     on_global<const R>(d, sd.rho[fc]), on_global<const R>(d, sd.phi[fc]),
-                                     on_global<const R>(d, sd.fmu), t);
+        kind = collide_node<D, PREC, false, 2>(kp, on_global<const S>(d, sd.f[pc]), on_global<const S>(d, sd.g[pc]),
+                                               on_global<S>(d, sd.f[1 - pc]), on_global<S>(d, sd.g[1 - pc]),
+                                               on_global<const R>(d, sd.rho[1 - fc]),
+                                               on_global<const R>(d, sd.phi[1 - fc]),
+                                               on_global<const R>(d, sd.rho[fc]), on_global<const R>(d, sd.phi[fc]),
+                                               on_global<const R>(d, sd.fmu), t);
     count_kinds(kind, s_cnt);
     __syncthreads();
     if (threadIdx.x < 3 && s_cnt[threadIdx.x])
@@ -1720,18 +1796,22 @@ static inline unsigned nblk(long long n, int t) { return (unsigned)((n + t - 1) 
 // (hipExtLaunchKernelGGL), so the interval is the kernels' run time, without
 // a marker packet (and the dispatch gap that comes with it) in between.
 static thread_local hipEvent_t t_stage_start = nullptr, t_stage_stop = nullptr;
+// within a two-kernel stage: the end of its first kernel, the start of its second
+static thread_local hipEvent_t t_sub_stop = nullptr, t_sub_start = nullptr;
 
-void set_stage_events(void *start, void *stop)
+void set_stage_events(void *start, void *stop, void *sub_stop, void *sub_start)
 {
     t_stage_start = (hipEvent_t)start;
     t_stage_stop = (hipEvent_t)stop;
+    t_sub_stop = (hipEvent_t)sub_stop;
+    t_sub_start = (hipEvent_t)sub_start;
 }
 
 template <typename F, typename... A>
 static void stage_launch(F kernel, dim3 grid, dim3 block, hipStream_t st, bool first, bool last, A... args)
 {
-    hipExtLaunchKernelGGL(kernel, grid, block, 0, st, first ? t_stage_start : nullptr,
-                          last ? t_stage_stop : nullptr, 0, args...);
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, st, first ? t_stage_start : t_sub_start,
+                          last ? t_stage_stop : t_sub_stop, 0, args...);
 }
 
 template <int D, int PREC>
@@ -1855,10 +1935,22 @@ static int split_t(const KParams &kp, const Buffers &b, int pc, int fc, hipStrea
                  (RP<PREC>)b.phi[1 - fc], (RP<PREC>)b.fmu, g.chunk);
     int r = LBM3_CHECK_LAUNCH();
     if (r) return r;
-    stage_launch(k_collide<3, PREC>, dim3((unsigned)collide_blocks(kp)), dim3(256), st, false, true, kp,
-                 (SP<PREC>)b.f[pc], (SP<PREC>)b.g[pc], (SP<PREC>)b.f[1 - pc], (SP<PREC>)b.g[1 - pc],
-                 (RP<PREC>)b.rho[1 - fc], (RP<PREC>)b.phi[1 - fc], (RP<PREC>)b.rho[fc], (RP<PREC>)b.phi[fc],
-                 (RP<PREC>)b.fmu, b.counters);
+    // the plane stride a multiple of the wave: planes are wave-uniform;
+    // tau_g = 1 with collisions: the stored g is not read
+    const bool uni = kp.PS % 64 == 0;
+    const bool gl = (kp.flags & 1u) || kp.inv_tau_g != 1.0;
+    auto go = [&](auto kern) {
+        stage_launch(kern, dim3((unsigned)collide_blocks(kp)), dim3(256), st, false, true, kp, (SP<PREC>)b.f[pc],
+                     (SP<PREC>)b.g[pc], (SP<PREC>)b.f[1 - pc], (SP<PREC>)b.g[1 - pc], (RP<PREC>)b.rho[1 - fc],
+                     (RP<PREC>)b.phi[1 - fc], (RP<PREC>)b.rho[fc], (RP<PREC>)b.phi[fc], (RP<PREC>)b.fmu, b.counters);
+    };
+    if (uni) {
+        if (gl) go(k_collide<3, PREC, true, 1>);
+        else go(k_collide<3, PREC, true, 0>);
+    } else {
+        if (gl) go(k_collide<3, PREC, false, 1>);
+        else go(k_collide<3, PREC, false, 0>);
+    }
     return LBM3_CHECK_LAUNCH();
 }
 

@@ -218,11 +218,13 @@ def lbm3_step(h, nsteps):
 def lbm3_step_profiled(h, nsteps, sample_every=1):
     """Run nsteps with events around the launches of every sample_every-th
     step; returns the mean device ms per launch of the moments, ghost-layer
-    (0 in 2D) and fused kernels, the span of the whole run in ms and the
-    number of sampled steps."""
-    ms = np.zeros(5)
+    (0 in 2D) and fused kernels (in 3D the stencil pass plus the collide
+    kernel, and each of the two alone), the span of the whole run in ms and
+    the number of sampled steps."""
+    ms = np.zeros(8)
     _check(h, lib().lbm3_step_profiled(h, int(nsteps), int(sample_every), _dp(ms)))
-    return {"moments": ms[0], "ghost": ms[1], "fused": ms[2], "span": ms[3], "sampled": int(ms[4])}
+    return {"moments": ms[0], "ghost": ms[1], "fused": ms[2], "span": ms[3], "sampled": int(ms[4]),
+            "stencil": ms[5], "collide": ms[6]}
 
 
 def lbm3_observe(h, what, rho_out=None, phi_out=None, f_out=None, g_out=None, check=True):
