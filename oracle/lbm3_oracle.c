@@ -636,11 +636,22 @@ static void pass_ghost(or_state *s)
                     /* Eqs. 45-46: c_ghost = c_first + grad_perp c, with
                      * grad_perp c = cot(theta) |grad_par c| toward the wall.
                      * reading: each field q gets cot(theta) (grad_par q . m),
-                     * m the unit in-plane direction of grad c. */
+                     * m the unit in-plane direction of grad c.
+                     * reading (the extrapolation is unbounded; at density
+                     * ratio 1000 and |cot theta| near 1 it can give a negative
+                     * ghost density on the gas side): each value is kept
+                     * within the bulk range widened to the first-layer value,
+                     * rho in [min(rho_1, rho_g), max(rho_1, rho_l)], phi in
+                     * [min(phi_1, -chi), max(phi_1, chi)]; inside that range
+                     * it is the plain extrapolation. */
                     if (ngc == 0.0) { s->rho[ng] = r0; s->phi[ng] = p0; continue; }
                     double m0 = gc[0] / ngc, m1 = gc[1] / ngc;
-                    s->rho[ng] = r0 + ct * (gr[0] * m0 + gr[1] * m1);
-                    s->phi[ng] = p0 + ct * (gp[0] * m0 + gp[1] * m1);
+                    double re = r0 + ct * (gr[0] * m0 + gr[1] * m1);
+                    double pe = p0 + ct * (gp[0] * m0 + gp[1] * m1);
+                    double rlo = fmin(r0, p->rho_g), rhi = fmax(r0, p->rho_l);
+                    double plo = fmin(p0, -p->chi), phi_ = fmax(p0, p->chi);
+                    s->rho[ng] = re < rlo ? rlo : (re > rhi ? rhi : re);
+                    s->phi[ng] = pe < plo ? plo : (pe > phi_ ? phi_ : pe);
                     continue;
                 }
                 /* geometric interpolation.  reading: the sampling point is

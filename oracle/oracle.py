@@ -380,3 +380,49 @@ def contact_angle_2d(c, wall_y=0.5, exclude=8.0, level=0.5, wall="low"):
     xc, yc, R = kasa_fit(xs[keep], ys[keep])
     h = (yc - wall_y) if wall == "low" else (wall_y - yc)
     return math.degrees(math.acos(max(-1.0, min(1.0, -h / R)))), (xc, yc, R)
+
+
+def contour_points_3d(c, level=0.5):
+    """Points where the field c (nz, ny, nx) crosses `level`, by linear
+    interpolation along the grid lines of the three axes (no wrap).  Returns
+    (x, y, z) arrays in lattice units."""
+    a = np.asarray(c, dtype=np.float64) - level
+    z, y, x = np.mgrid[0:a.shape[0], 0:a.shape[1], 0:a.shape[2]].astype(np.float64)
+    xs, ys, zs = [], [], []
+    for ax in (2, 1, 0):
+        lo = [slice(None)] * 3
+        hi = [slice(None)] * 3
+        lo[ax] = slice(0, -1)
+        hi[ax] = slice(1, None)
+        a0, a1 = a[tuple(lo)], a[tuple(hi)]
+        cross = a0 * a1 < 0.0
+        t = np.zeros_like(a0)
+        t[cross] = a0[cross] / (a0[cross] - a1[cross])
+        pos = [x[tuple(lo)], y[tuple(lo)], z[tuple(lo)]]
+        pos[2 - ax] = pos[2 - ax] + t
+        xs.append(pos[0][cross]); ys.append(pos[1][cross]); zs.append(pos[2][cross])
+    return np.concatenate(xs), np.concatenate(ys), np.concatenate(zs)
+
+
+def kasa_fit_sphere(xs, ys, zs):
+    """Algebraic (Kasa) least-squares sphere: x^2 + y^2 + z^2 + D x + E y + F z
+    + G = 0."""
+    A = np.stack([xs, ys, zs, np.ones_like(xs)], axis=1)
+    rhs = -(xs ** 2 + ys ** 2 + zs ** 2)
+    sol, *_ = np.linalg.lstsq(A, rhs, rcond=None)
+    Dd, E, F, G = sol
+    xc, yc, zc = -Dd / 2, -E / 2, -F / 2
+    R = math.sqrt(xc ** 2 + yc ** 2 + zc ** 2 - G)
+    return xc, yc, zc, R
+
+
+def contact_angle_3d(c, wall_z=0.5, exclude=8.0, level=0.5, wall="low"):
+    """Contact angle (degrees) measured inside the phase of concentration c
+    (nz, ny, nx) for a sessile drop on the wall plane z = wall_z: sphere fit
+    to the c = 0.5 iso-points farther than `exclude` from the wall plane,
+    theta = arccos(-h/R), h the centre height above the wall plane."""
+    xs, ys, zs = contour_points_3d(c, level)
+    keep = np.abs(zs - wall_z) > exclude
+    xc, yc, zc, R = kasa_fit_sphere(xs[keep], ys[keep], zs[keep])
+    h = (zc - wall_z) if wall == "low" else (wall_z - zc)
+    return math.degrees(math.acos(max(-1.0, min(1.0, -h / R)))), (xc, yc, zc, R)

@@ -690,11 +690,17 @@ __device__ __forceinline__ void ghost_value(const KParams &kp, const R (&cot)[3]
     const R *gc = cls == 2 ? gp : gr;
     R ngc = cls == 2 ? ngp : ngr;
     if (kp.wetting == 2) {
-        // geometric extrapolation (Eqs. 45-46), per field along m
+        // geometric extrapolation (Eqs. 45-46), per field along m, kept
+        // within the bulk range widened to the first-layer value (the plain
+        // extrapolation can give a negative gas-side density)
         if (ngc != (R)0) {
             R m0 = gc[0] / ngc, m1 = gc[1] / ngc;
-            out_r = r0 + ct * (gr[0] * m0 + gr[1] * m1);
-            out_p = p0 + ct * (gp[0] * m0 + gp[1] * m1);
+            const R re = r0 + ct * (gr[0] * m0 + gr[1] * m1);
+            const R pe = p0 + ct * (gp[0] * m0 + gp[1] * m1);
+            const R rlo = fmin(r0, (R)kp.rho_g), rhi = fmax(r0, (R)kp.rho_l);
+            const R plo = fmin(p0, -chi), phi_ = fmax(p0, chi);
+            out_r = re < rlo ? rlo : (re > rhi ? rhi : re);
+            out_p = pe < plo ? plo : (pe > phi_ ? phi_ : pe);
         }
     } else if constexpr (D == 2) {
         // shift by cot(theta) toward the measuring phase (+grad c)
@@ -1286,19 +1292,286 @@ k_fused_batch(const SimDesc *__restrict__ d, const int *__restrict__ sim, int ph
                                      local / sd.ntiles);
 }
 
-// Stencil pass of the two-kernel 3D step: the fused march without the
-// populations, writing F and mu_phi.
-template <int D, int PREC, int TX, int TY, int NTH>
-__global__ void LBM3_FUSED_ATTR
+// ------------------------------------------------------ 3D stencil pass --
+// The 1D factors of the isotropic D3Q27 stencils: with w_i the product of
+// w1(c) = 2/3, 1/6, 1/6 over the axes, sum_i w_i q(x + c_i) = S_x S_y S_z q,
+// grad_x q = 3 sum_i w_i c_ix q(x + c_i) = D_x S_y S_z q (and cyclic), and
+// lap q = 6 (S_x S_y S_z q - q), with S = (1/6, 2/3, 1/6) and D = (-1/2, 0,
+// 1/2).  The divergence of -P uses the same gradient stencil on each column.
+template <typename R> __device__ __forceinline__ R sm3(R m, R c, R p)
+{
+    return (R)(2.0 / 3.0) * c + (R)(1.0 / 6.0) * (m + p);
+}
+template <typename R> __device__ __forceinline__ R df3(R m, R p) { return (R)0.5 * (p - m); }
+
+// Stencil pass of the two-kernel 3D step (Sec. II A-C, Sec. IV): per block an
+// in-plane TX x TY tile marching along the wall axis over the planes of its
+// chunk.  Each plane q: the z factors of the rho, phi stencils from three
+// planes of fields held in registers (tile + halo 2), then the y and the x
+// factors through LDS, giving grad, lap of rho and phi on tile + halo 1, mu
+// and -P there (Eqs. 11-20), kept in registers for three planes; then the
+// force on the tile for the plane below: the z factors of div(-P) in
+// registers, y and x through LDS, plus the ideal part as the lattice
+// divergence of the link pressure of sqrt(rho), and the first-fluid-layer
+// wall rule and force-method wall force of Sec. IV.  Writes F and mu_phi
+// ([D + 1][N]).
+template <int PREC, int TX, int TY>
+__device__ __forceinline__ void force_march3(const KParams &kp, const typename Ty<PREC>::R *__restrict__ rho,
+                                             const typename Ty<PREC>::R *__restrict__ phi,
+                                             typename Ty<PREC>::R *__restrict__ fmu, int chunk, int bx, int by)
+{
+    using R = typename Ty<PREC>::R;
+    constexpr int NT = TX * TY;
+    constexpr int W2 = TX + 4, H2 = TY + 4, E2 = W2 * H2;  // tile + halo 2
+    constexpr int W1 = TX + 2, H1 = TY + 2, E1 = W1 * H1;  // tile + halo 1
+    constexpr int EY = W2 * (TY + 2);                      // y pass of the fields
+    constexpr int ED = W1 * TY;                            // y pass of the divergence
+    constexpr int FE = (E2 + NT - 1) / NT, TE = (E1 + NT - 1) / NT, YE = (EY + NT - 1) / NT, DE = (ED + NT - 1) / NT;
+    __shared__ R s_z[4][E2];        // S_z rho, D_z rho, S_z phi, D_z phi
+    __shared__ R s_c[2][E2];        // rho, phi of the plane
+    __shared__ R s_q[3][E2];        // 1/sqrt(rho) of three planes (ring)
+    __shared__ R s_y[6][EY];        // S_y S_z rho, D_y S_z rho, S_y D_z rho, same for phi
+    __shared__ R s_w[8][E1];        // S_z of -P xx xy xz yy yz, D_z of -P xz yz zz (first layer: -P xx..yz)
+    __shared__ R s_mu[E1];          // mu_phi of the output plane
+    __shared__ R s_d[6][ED];        // S_y S_z (-P x.), D_y S_z (-P y.) + S_y D_z (-P z.)
+
+    const int tid = threadIdx.x;
+    const int nx = kp.nx, ny = kp.ny, nw = kp.nw;
+    const unsigned N = (unsigned)kp.N, PS = (unsigned)kp.PS;
+    const bool walls = kp.walls != 0;
+    const int ntx = (nx + TX - 1) / TX;
+    const int x0 = (bx % ntx) * TX, y0 = (bx / ntx) * TY;
+    int pb, pe;
+    chunk_range(kp, 0, chunk, by, pb, pe);
+    if (pb >= pe) return;
+    Thermo<R> th;
+    th.load(kp);
+
+    // in-plane indices of this thread's field elements (tile + halo 2)
+    unsigned fidx[FE];
+#pragma unroll
+    for (int m = 0; m < FE; ++m) {
+        int k = tid + m * NT;
+        k = k < E2 ? k : E2 - 1;
+        fidx[m] = (unsigned)wrapl(x0 + k % W2 - 2, nx) + (unsigned)nx * (unsigned)wrapl(y0 + k / W2 - 2, ny);
+    }
+    auto plane_of = [&](int q) { return walls ? (q < 0 ? 0 : (q > nw - 1 ? nw - 1 : q)) : wrapl(q, nw); };
+    auto fluid = [&](int q) { return !walls || (q >= 1 && q <= nw - 2); };
+
+    // fields of three consecutive planes in registers, plus the next plane's
+    // loads in flight
+    R fr[3][FE], fp[3][FE], nr[FE], np_[FE];
+    auto load = [&](int q, R *dr, R *dp) {
+        const unsigned base = (unsigned)plane_of(q) * PS;
+#pragma unroll
+        for (int m = 0; m < FE; ++m) {
+            dr[m] = rho[base + fidx[m]];
+            dp[m] = phi[base + fidx[m]];
+        }
+    };
+    // -P (xx xy xz yy yz zz) and mu_phi of the thread's tile + halo 1
+    // elements on three planes
+    R tp[3][TE][6], tm[3][TE];
+
+    // Field stage of plane q (fields of q - 1, q, q + 1 in fr/fp[0..2]):
+    // 1/sqrt(rho) into the ring; on fluid planes grad, lap, mu and -P into
+    // tp/tm[2] (after shifting the register ring down).
+    auto field_stage = [&](int q) {
+        __syncthreads();
+        const int sq = wrapl(q, 3);
+#pragma unroll
+        for (int m = 0; m < FE; ++m) {
+            const int k = tid + m * NT;
+            if (E2 % NT == 0 || k < E2) {
+                s_q[sq][k] = fdiv((R)1, fsqrt(fr[1][m]));
+                s_c[0][k] = fr[1][m];
+                s_c[1][k] = fp[1][m];
+                s_z[0][k] = sm3(fr[0][m], fr[1][m], fr[2][m]);
+                s_z[1][k] = df3(fr[0][m], fr[2][m]);
+                s_z[2][k] = sm3(fp[0][m], fp[1][m], fp[2][m]);
+                s_z[3][k] = df3(fp[0][m], fp[2][m]);
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < TE; ++e) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) { tp[0][e][c] = tp[1][e][c]; tp[1][e][c] = tp[2][e][c]; }
+            tm[0][e] = tm[1][e];
+            tm[1][e] = tm[2][e];
+        }
+        if (!fluid(q)) return;  // uniform: a ghost layer has no -P
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < YE; ++m) {
+            const int k = tid + m * NT;
+            if (EY % NT == 0 || k < EY) {
+                const int c = k + W2;  // centre in tile + halo 2 (rows 1 .. TY + 2)
+                s_y[0][k] = sm3(s_z[0][c - W2], s_z[0][c], s_z[0][c + W2]);
+                s_y[1][k] = df3(s_z[0][c - W2], s_z[0][c + W2]);
+                s_y[2][k] = sm3(s_z[1][c - W2], s_z[1][c], s_z[1][c + W2]);
+                s_y[3][k] = sm3(s_z[2][c - W2], s_z[2][c], s_z[2][c + W2]);
+                s_y[4][k] = df3(s_z[2][c - W2], s_z[2][c + W2]);
+                s_y[5][k] = sm3(s_z[3][c - W2], s_z[3][c], s_z[3][c + W2]);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < TE; ++e) {
+            const int k = tid + e * NT;
+            if (E1 % NT != 0 && k >= E1) continue;  // only the first waves hold a halo element
+            const int x1 = k % W1, y1 = k / W1;
+            const int cy = y1 * W2 + x1 + 1;  // in the y-pass arrays (row y1 = halo-2 row y1 + 1)
+            const int c2 = (y1 + 1) * W2 + x1 + 1;
+            const R r0 = s_c[0][c2], p0 = s_c[1][c2];
+            R G[3], H[3];
+            G[0] = df3(s_y[0][cy - 1], s_y[0][cy + 1]);
+            G[1] = sm3(s_y[1][cy - 1], s_y[1][cy], s_y[1][cy + 1]);
+            G[2] = sm3(s_y[2][cy - 1], s_y[2][cy], s_y[2][cy + 1]);
+            const R sr = sm3(s_y[0][cy - 1], s_y[0][cy], s_y[0][cy + 1]);
+            H[0] = df3(s_y[3][cy - 1], s_y[3][cy + 1]);
+            H[1] = sm3(s_y[4][cy - 1], s_y[4][cy], s_y[4][cy + 1]);
+            H[2] = sm3(s_y[5][cy - 1], s_y[5][cy], s_y[5][cy + 1]);
+            const R sp = sm3(s_y[3][cy - 1], s_y[3][cy], s_y[3][cy + 1]);
+            const R Lr = (R)6 * (sr - r0), Lp = (R)6 * (sp - p0);
+            R mur, mup, mP[6];
+            thermo<3, R>(th, r0, p0, G, H, Lr, Lp, mur, mup, mP);
+#pragma unroll
+            for (int c = 0; c < 6; ++c) tp[2][e][c] = mP[c];
+            tm[2][e] = mup;
+        }
+    };
+
+    // prologue: fields of pb - 2 .. pb + 1, the field stages of pb - 1, pb,
+    // and the loads of pb + 2 in flight
+    load(pb - 2, fr[0], fp[0]);
+    load(pb - 1, fr[1], fp[1]);
+    load(pb, fr[2], fp[2]);
+    load(pb + 1, nr, np_);
+    field_stage(pb - 1);
+#pragma unroll
+    for (int m = 0; m < FE; ++m) {
+        fr[0][m] = fr[1][m]; fr[1][m] = fr[2][m]; fr[2][m] = nr[m];
+        fp[0][m] = fp[1][m]; fp[1][m] = fp[2][m]; fp[2][m] = np_[m];
+    }
+    load(pb + 2, nr, np_);
+    field_stage(pb);
+
+    const int tx = tid % TX, ty = tid / TX;
+    const bool active = x0 + tx < nx && y0 + ty < ny;
+    const unsigned own = (unsigned)(x0 + tx < nx ? x0 + tx : nx - 1) + (unsigned)nx * (unsigned)(y0 + ty < ny ? y0 + ty : ny - 1);
+    const int oq = (ty + 2) * W2 + tx + 2;  // own node in tile + halo 2
+    const int o1 = (ty + 1) * W1 + tx + 1;  // own node in tile + halo 1
+
+    for (int p = pb; p < pe; ++p) {
+        // fields of p, p + 1, p + 2 and the loads of p + 3 in flight
+#pragma unroll
+        for (int m = 0; m < FE; ++m) {
+            fr[0][m] = fr[1][m]; fr[1][m] = fr[2][m]; fr[2][m] = nr[m];
+            fp[0][m] = fp[1][m]; fp[1][m] = fp[2][m]; fp[2][m] = np_[m];
+        }
+        if (p + 1 < pe) load(p + 3, nr, np_);
+        field_stage(p + 1);
+        // -P of p - 1, p, p + 1 in tp[0..2]: z factors of the divergence
+        const bool first = walls && (p == 1 || p == nw - 2);
+#pragma unroll
+        for (int e = 0; e < TE; ++e) {
+            const int k = tid + e * NT;
+            if (E1 % NT == 0 || k < E1) {
+                if (first) {
+                    // wall rule: in-layer central differences of -P only
+#pragma unroll
+                    for (int c = 0; c < 5; ++c) s_w[c][k] = tp[1][e][c];
+                } else {
+                    s_w[0][k] = sm3(tp[0][e][0], tp[1][e][0], tp[2][e][0]);  // xx
+                    s_w[1][k] = sm3(tp[0][e][1], tp[1][e][1], tp[2][e][1]);  // xy
+                    s_w[2][k] = sm3(tp[0][e][2], tp[1][e][2], tp[2][e][2]);  // xz
+                    s_w[3][k] = sm3(tp[0][e][3], tp[1][e][3], tp[2][e][3]);  // yy
+                    s_w[4][k] = sm3(tp[0][e][4], tp[1][e][4], tp[2][e][4]);  // yz
+                    s_w[5][k] = df3(tp[0][e][2], tp[2][e][2]);               // xz
+                    s_w[6][k] = df3(tp[0][e][4], tp[2][e][4]);               // yz
+                    s_w[7][k] = df3(tp[0][e][5], tp[2][e][5]);               // zz
+                }
+                s_mu[k] = tm[1][e];
+            }
+        }
+        __syncthreads();
+        if (!first) {
+#pragma unroll
+            for (int m = 0; m < DE; ++m) {
+                const int k = tid + m * NT;
+                if (ED % NT == 0 || k < ED) {
+                    const int c = k + W1;
+                    s_d[0][k] = sm3(s_w[0][c - W1], s_w[0][c], s_w[0][c + W1]);  // S_y S_z xx
+                    s_d[1][k] = sm3(s_w[1][c - W1], s_w[1][c], s_w[1][c + W1]);  // S_y S_z xy
+                    s_d[2][k] = sm3(s_w[2][c - W1], s_w[2][c], s_w[2][c + W1]);  // S_y S_z xz
+                    s_d[3][k] = df3(s_w[1][c - W1], s_w[1][c + W1]) + sm3(s_w[5][c - W1], s_w[5][c], s_w[5][c + W1]);
+                    s_d[4][k] = df3(s_w[3][c - W1], s_w[3][c + W1]) + sm3(s_w[6][c - W1], s_w[6][c], s_w[6][c + W1]);
+                    s_d[5][k] = df3(s_w[4][c - W1], s_w[4][c + W1]) + sm3(s_w[7][c - W1], s_w[7][c], s_w[7][c + W1]);
+                }
+            }
+            __syncthreads();
+        }
+        if (active) {
+            R F[3];
+            const int sm = wrapl(p - 1, 3), s0 = wrapl(p, 3), sp = wrapl(p + 1, 3);
+            // link pressure 2 rho_x rho_y / (rho_x + rho_y + 4 sqrt(rho_x rho_y))
+            // = 2 / (i_x^2 + i_y^2 + 4 i_x i_y), i = 1/sqrt(rho)
+            const R i0 = s_q[s0][oq], a0 = i0 * i0, c0 = (R)4 * i0;
+            auto hlink = [&](R i1) { return fdiv((R)1, i1 * (i1 + c0) + a0); };  // half the link pressure
+            if (first) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    // -P_ax at x +- 1 and -P_ay at y +- 1 (sym order xx xy xz yy yz)
+                    const int cx = a, cy = a == 0 ? 1 : (a == 1 ? 3 : 4);
+                    F[a] = (R)0.5 * (s_w[cx][o1 + 1] - s_w[cx][o1 - 1]) + (R)0.5 * (s_w[cy][o1 + W1] - s_w[cy][o1 - W1]);
+                }
+                F[0] += (R)2 * (hlink(s_q[s0][oq + 1]) - hlink(s_q[s0][oq - 1]));
+                F[1] += (R)2 * (hlink(s_q[s0][oq + W2]) - hlink(s_q[s0][oq - W2]));
+                F[2] += (R)2 * (hlink(s_q[sp][oq]) - hlink(s_q[sm][oq]));
+            } else {
+                const int od = ty * W1 + tx + 1;
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    F[a] = df3(s_d[a][od - 1], s_d[a][od + 1]) + sm3(s_d[3 + a][od - 1], s_d[3 + a][od], s_d[3 + a][od + 1]);
+#pragma unroll
+                for (int i = 0; i < 27; ++i) {
+                    if (i == 13) continue;
+                    const int cx = cdir(3, i, 0), cy = cdir(3, i, 1), cz = cdir(3, i, 2);
+                    const int sl = cz < 0 ? sm : (cz > 0 ? sp : s0);
+                    const R hl = hlink(s_q[sl][oq + cx + cy * W2]);
+                    const R w12 = (R)(12.0 * wgt(3, i));
+                    if (cx) F[0] += (R)cx * w12 * hl;
+                    if (cy) F[1] += (R)cy * w12 * hl;
+                    if (cz) F[2] += (R)cz * w12 * hl;
+                }
+            }
+            if (walls && kp.wetting == 0 && (p == 2 || p == nw - 3)) {
+                const unsigned n = (unsigned)p * PS + own;
+                const R r0 = rho[n], p0 = phi[n];
+                const R rrel = (r0 - (R)kp.rho_g) * th.inv_drho, prel = p0 * th.inv_chi;
+                if (p == 2) F[2] -= (R)(1.0 / 6.0) * rrel * ((R)kp.kw[0][0] + prel * (R)kp.kw[0][1]);
+                if (p == nw - 3) F[2] += (R)(1.0 / 6.0) * rrel * ((R)kp.kw[1][0] + prel * (R)kp.kw[1][1]);
+            }
+            const unsigned n = (unsigned)p * PS + own;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) fmu[(size_t)a * N + n] = F[a];
+            fmu[(size_t)3 * N + n] = s_mu[o1];
+        }
+    }
+}
+
+#define LBM3_STENCIL_ATTR __launch_bounds__(TX * TY)
+
+template <int PREC, int TX, int TY>
+__global__ void LBM3_STENCIL_ATTR
 k_stencil(KParams kp, typename Ty<PREC>::R *__restrict__ rho, typename Ty<PREC>::R *__restrict__ phi,
           typename Ty<PREC>::R *__restrict__ fmu, int chunk)
 {
-    fused_tile<D, PREC, TX, TY, NTH, true>(kp, nullptr, nullptr, nullptr, nullptr, rho, phi, nullptr, nullptr,
-                                           nullptr, chunk, blockIdx.x, blockIdx.y, fmu);
+    force_march3<PREC, TX, TY>(kp, rho, phi, fmu, chunk, blockIdx.x, blockIdx.y);
 }
 
-template <int D, int PREC, int TX, int TY, int NTH>
-__global__ void LBM3_FUSED_ATTR
+template <int PREC, int TX, int TY>
+__global__ void LBM3_STENCIL_ATTR
 k_stencil_batch(const SimDesc *__restrict__ d, const int *__restrict__ sim, int phase)
 {
     using R = typename Ty<PREC>::R;
@@ -1306,9 +1579,8 @@ k_stencil_batch(const SimDesc *__restrict__ d, const int *__restrict__ sim, int 
     const KParams &kp = sd.kp;
     const int fc = sd.fc ^ phase;
     const int local = blockIdx.x - sd.fblk0;
-    fused_tile<D, PREC, TX, TY, NTH, true>(kp, nullptr, nullptr, nullptr, nullptr, on_global<R>(d, sd.rho[1 - fc]),
-                                           on_global<R>(d, sd.phi[1 - fc]), nullptr, nullptr, nullptr, sd.chunk,
-                                           local % sd.ntiles, local / sd.ntiles, on_global<R>(d, sd.fmu));
+    force_march3<PREC, TX, TY>(kp, on_global<R>(d, sd.rho[1 - fc]), on_global<R>(d, sd.phi[1 - fc]),
+                               on_global<R>(d, sd.fmu), sd.chunk, local % sd.ntiles, local / sd.ntiles);
 }
 
 // Raw buffer access to one array of n elements at a uniform base: the
@@ -1523,13 +1795,15 @@ k_collide_batch(const SimDesc *__restrict__ d, const int *__restrict__ sim, int 
     const long long count = kp.walls ? kp.N - 2 * kp.PS : kp.N;
     const long long t = (long long)(blockIdx.x - sd.cblk0) * blockDim.x + threadIdx.x;
     int kind = -1;
-    if (t < count)
-        kind = collide_node<D, PREC, false, 2>(kp, on_global<const S>(d, sd.f[pc]), on_global<const S>(d, sd.g[pc]),
-                                               on_global<S>(d, sd.f[1 - pc]), on_global<S>(d, sd.g[1 - pc]),
-                                               on_global<const R>(d, sd.rho[1 - fc]),
-                                               on_global<const R>(d, sd.phi[1 - fc]),
-                                               on_global<const R>(d, sd.rho[fc]), on_global<const R>(d, sd.phi[fc]),
-                                               on_global<const R>(d, sd.fmu), t);
+    // the same arithmetic either way; a plane stride that is a multiple of
+    // the wave makes the bounce-back branches scalar (block-uniform test)
+    auto node = [&](auto uni) {
+        return collide_node<D, PREC, decltype(uni)::value, 2>(
+            kp, on_global<const S>(d, sd.f[pc]), on_global<const S>(d, sd.g[pc]), on_global<S>(d, sd.f[1 - pc]),
+            on_global<S>(d, sd.g[1 - pc]), on_global<const R>(d, sd.rho[1 - fc]), on_global<const R>(d, sd.phi[1 - fc]),
+            on_global<const R>(d, sd.rho[fc]), on_global<const R>(d, sd.phi[fc]), on_global<const R>(d, sd.fmu), t);
+    };
+    if (t < count) kind = kp.PS % 64 == 0 ? node(std::true_type{}) : node(std::false_type{});
     count_kinds(kind, s_cnt);
     __syncthreads();
     if (threadIdx.x < 3 && s_cnt[threadIdx.x])
@@ -1931,7 +2205,7 @@ static int split_t(const KParams &kp, const Buffers &b, int pc, int fc, hipStrea
 {
     FusedGeom g = fused_geometry(kp, PREC);
     dim3 grid((unsigned)g.ntiles, (unsigned)g.nchunks);
-    stage_launch(k_stencil<3, PREC, TX, TY, NTH>, grid, dim3(NTH), st, true, false, kp, (RP<PREC>)b.rho[1 - fc],
+    stage_launch(k_stencil<PREC, TX, TY>, grid, dim3(NTH), st, true, false, kp, (RP<PREC>)b.rho[1 - fc],
                  (RP<PREC>)b.phi[1 - fc], (RP<PREC>)b.fmu, g.chunk);
     int r = LBM3_CHECK_LAUNCH();
     if (r) return r;
@@ -2055,9 +2329,9 @@ int launch_fused_batch(int cls, int prec, const SimDesc *d, const int *sim, long
         else if (prec == P32) k_fused_batch<3, P32, 32, 16, 512><<<grid, 512, 0, st>>>(d, sim, phase);
         else k_fused_batch<3, P16, 32, 16, 512><<<grid, 512, 0, st>>>(d, sim, phase);
     } else {
-        if (prec == P64) k_stencil_batch<3, P64, 32, 4, 128><<<grid, 128, 0, st>>>(d, sim, phase);
-        else if (prec == P32) k_stencil_batch<3, P32, 32, 8, 256><<<grid, 256, 0, st>>>(d, sim, phase);
-        else k_stencil_batch<3, P16, 32, 8, 256><<<grid, 256, 0, st>>>(d, sim, phase);
+        if (prec == P64) k_stencil_batch<P64, 32, 4><<<grid, 128, 0, st>>>(d, sim, phase);
+        else if (prec == P32) k_stencil_batch<P32, 32, 8><<<grid, 256, 0, st>>>(d, sim, phase);
+        else k_stencil_batch<P16, 32, 8><<<grid, 256, 0, st>>>(d, sim, phase);
     }
     return LBM3_CHECK_LAUNCH();
 }

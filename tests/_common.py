@@ -1,5 +1,7 @@
 """Shared set-ups for the GPU parity tests: the same seeded inputs and the
 same parameters go to the HIP library and to the CPU oracle."""
+import sys
+
 import numpy as np
 
 from oracle import oracle as O
@@ -37,3 +39,42 @@ def fluid(arr, walls, D):
     if not walls:
         return arr
     return arr[1:-1] if D == 2 else arr[1:-1]
+
+
+def say(*a):
+    """Name the GPU case before it runs (flushed, so a failing run shows it)."""
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def run_both(p, rho0, phi0, steps, gpu_chunks=None, oracle=True):
+    """The library (through the C ABI) and the oracle from the same fields and
+    parameters, `steps` steps each; returns (sim, oracle sim or None)."""
+    from paper_1904_06881_amd import lbm3 as L
+    say("run", "lattice", p.lattice, "n", list(p.n), "prec", p.precision, "wet", p.wetting,
+        "walls", p.walls, "steps", steps)
+    sim = L.Sim(p)
+    sim.init(rho0, phi0)
+    if gpu_chunks:
+        for c in gpu_chunks:
+            sim.step(c)
+    else:
+        sim.step(steps)
+    ora = None
+    if oracle:
+        ora = O.Sim(oracle_params_from(p, sim.derived))
+        ora.init(rho0, phi0)
+        ora.step(steps)
+    return sim, ora
+
+
+def conc_err(sim, ora, walls=True):
+    """Max-abs difference of C1, C2, C3 over the fluid nodes."""
+    d = sim.derived
+    rg, pg = sim.fields()
+    ro, po = ora.fields()
+    sl = (slice(None), slice(1, -1)) if walls else (slice(None),)
+    cg = conc(rg, pg, d.rho_l, d.rho_g)[sl]
+    co = conc(ro, po, d.rho_l, d.rho_g)[sl]
+    assert np.all(np.isfinite(cg))
+    return float(np.abs(cg - co).max())

@@ -532,6 +532,21 @@ def test_kasa_fit_exact_on_circle():
         assert abs(got - th) < 0.3, (th, got)
 
 
+def test_kasa_sphere_fit_on_spherical_cap():
+    """3D contact-angle measurement: a spherical-cap field (tanh profile of
+    width 4 around a sphere of radius 16 cut by the wall plane z = 0.5) gives
+    back its angle, centre and radius; points are taken on x, y and z grid
+    lines."""
+    z, y, x = np.mgrid[0:40, 0:64, 0:64].astype(float)
+    for th in (50.0, 90.0, 130.0):
+        R = 16.0
+        zc = 0.5 - R * math.cos(math.radians(th))
+        c = I.profile(R - np.sqrt((x - 31.3) ** 2 + (y - 32.6) ** 2 + (z - zc) ** 2), 4.0)
+        got, (xc, yc, zf, Rf) = O.contact_angle_3d(c, wall_z=0.5, exclude=4.0)
+        assert abs(got - th) < 0.1, (th, got)
+        assert abs(xc - 31.3) < 0.01 and abs(yc - 32.6) < 0.01 and abs(Rf - R) < 0.05
+
+
 def test_alpha_small_deviation_root():
     """Below the shortcut threshold alpha is the expansion of the entropy
     equation about alpha = 2; it agrees with the Newton root of the same

@@ -153,6 +153,28 @@ def test_extrapolation_2d_per_field():
         assert rg[i] > r1[i]
 
 
+def test_extrapolation_2d_stays_in_the_bulk_range():
+    """At theta21 = 150 degrees the plain extrapolation q + cot(theta) dq/dx m
+    gives negative densities on the gas side of a gas-liquid-2 interface;
+    the ghost value is then the lower end of the bulk range widened to the
+    first-layer value, min(rho_1, rho_g), and elsewhere the plain formula."""
+    s = tanh_row(32, 15.7)
+    th = (150.0, 150.0, 150.0)
+    (r1, p1), (rg, pg) = ghost_2d(*rows_to_grid(RHO_G + DRHO * s, CHI * s), wetting=O.GEOM_EXTRAP, theta=th)
+    clamped = 0
+    for i in range(2, 30):
+        gr = 0.5 * (r1[i + 1] - r1[i - 1])
+        if abs(gr) < 1e-12:
+            continue
+        plain = r1[i] + cot(150.0) * abs(gr)
+        lo, hi = min(r1[i], RHO_G), max(r1[i], RHO_L)
+        want = min(max(plain, lo), hi)
+        assert abs(rg[i] - want) < 1e-15
+        clamped += plain < lo
+    assert clamped >= 2
+    assert (rg > 0).all()
+
+
 # ------------------------------------------------------------------- 3D ----
 NX3, NY3, NZ3 = 16, 16, 6
 I3, J3 = 6, 7
