@@ -207,6 +207,20 @@ lbm3_status lbm3_batch_workspace(lbm3 *const *hs, int32_t n, size_t *bytes);
 lbm3_status lbm3_step_batch(lbm3 *const *hs, int32_t n, int64_t nsteps, void *stream, void *ws,
                             size_t ws_bytes);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): as
+ * lbm3_step_batch, but the descriptor image goes into a static device array
+ * of the library (LBM3_STEP_BATCH_STATIC_MAX_BYTES, 8 MiB, one per GPU,
+ * held until the process ends) instead of a caller workspace; no device or
+ * host-pinned memory is allocated.  Uses the array of the device
+ * current at the call (the handles' device).  Every call on one GPU shares
+ * that GPU's array: calls that overlap on one GPU (other threads or
+ * streams) race and must be serialised by the caller.  LBM3_EINVAL when the
+ * image (lbm3_batch_workspace) exceeds the array or on bad handles,
+ * LBM3_EDEVICE on a failed copy or launch. */
+#define LBM3_STEP_BATCH_STATIC_MAX_BYTES ((size_t)8 << 20)
+lbm3_status lbm3_step_batch_static(lbm3 *const *hs, int32_t n, int64_t nsteps, void *stream);
+
 /* ------------------------------------------------------------- serving ---
  * Continuous batching: requests (parameters, initial fields, step count)
  * queue on the host.  Resident simulations are split by size into lanes

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -558,6 +559,61 @@ lbm3_status lbm3_step_batch(lbm3 *const *hs, int32_t n, int64_t nsteps, void *st
         hipStreamSynchronize(s) != hipSuccess)
         return LBM3_EDEVICE;
     return lbm3b::enqueue(hs, n, img, ws, 0, nsteps, s);
+}
+
+}  // extern "C"
+
+// ------------------------------------------- batched stepping, no workspace
+// The descriptor image of lbm3_step_batch_static lives in this file-scope
+// device array instead of a caller workspace: every device the library runs
+// on holds its own copy until the process ends.  Host code never passes the
+// array's name to a kernel or a copy (in host code it is only a stand-in
+// for the symbol): the device address comes from hipGetSymbolAddress, once
+// per device with that device current, and is kept per device.
+namespace {
+constexpr size_t kStaticImageBytes = LBM3_STEP_BATCH_STATIC_MAX_BYTES;
+__device__ __align__(256) unsigned char scratch[kStaticImageBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+lbm3_status scratch_address(void **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return LBM3_EDEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return LBM3_EDEVICE;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return LBM3_OK;
+}
+}  // namespace
+
+extern "C" {
+
+lbm3_status lbm3_step_batch_static(lbm3 *const *hs, int32_t n, int64_t nsteps, void *stream)
+{
+    if (nsteps < 0) return LBM3_EINVAL;
+    lbm3b::Image img;
+    lbm3_status st = lbm3b::build(hs, n, img);
+    if (st != LBM3_OK) return st;
+    if (img.bytes.size() > kStaticImageBytes) {
+        for (int i = 0; i < n; ++i)
+            hs[i]->err = "batch image of " + std::to_string(img.bytes.size()) + " bytes exceeds the static " +
+                         std::to_string(kStaticImageBytes) + "-byte scratch array";
+        return LBM3_EINVAL;
+    }
+    void *dev_img = nullptr;
+    if ((st = scratch_address(&dev_img)) != LBM3_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    // the image is in pageable memory: wait for the copy before it goes
+    if (hipMemcpyAsync(dev_img, img.bytes.data(), img.bytes.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return LBM3_EDEVICE;
+    return lbm3b::enqueue(hs, n, img, dev_img, 0, nsteps, s);
 }
 
 }  // extern "C"

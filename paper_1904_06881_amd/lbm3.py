@@ -71,7 +71,7 @@ EXPORTS = ["lbm3_footprint", "lbm3_resolve", "lbm3_create", "lbm3_init", "lbm3_s
            "lbm3_last_error", "lbm3_batch_workspace", "lbm3_step_batch",
            "lbm3_server_request_bytes", "lbm3_server_create", "lbm3_server_submit",
            "lbm3_server_run", "lbm3_server_poll", "lbm3_server_fields", "lbm3_server_clock",
-           "lbm3_server_destroy"]
+           "lbm3_server_destroy", "lbm3_step_batch_static"]
 
 
 class Lbm3Error(RuntimeError):
@@ -116,6 +116,8 @@ def lib():
         L.lbm3_batch_workspace.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(C.c_size_t)]
         L.lbm3_step_batch.restype = C.c_int
         L.lbm3_step_batch.argtypes = [C.POINTER(vp), C.c_int32, C.c_int64, vp, vp, C.c_size_t]
+        L.lbm3_step_batch_static.restype = C.c_int
+        L.lbm3_step_batch_static.argtypes = [C.POINTER(vp), C.c_int32, C.c_int64, vp]
         L.lbm3_server_request_bytes.restype = C.c_size_t
         L.lbm3_server_request_bytes.argtypes = [C.POINTER(lbm3_params)]
         L.lbm3_server_create.restype = C.c_int
@@ -332,6 +334,20 @@ def step_batch(sims, nsteps, stream=None):
     if st != 0:
         raise Lbm3Error(st, "batched step failed")
     return ws  # keep alive until the work is done
+
+
+def step_batch_static(sims, nsteps, stream=None):
+    """As step_batch, with the descriptor image in the library's static device
+    array (lbm3_step_batch_static): no workspace is allocated."""
+    n = len(sims)
+    hs = (C.c_void_p * n)(*[s.h for s in sims])
+    stream = stream if stream is not None else sims[0].stream
+    st = lib().lbm3_step_batch_static(hs, n, int(nsteps), C.c_void_p(stream.cuda_stream))
+    if st != 0:
+        raise Lbm3Error(st, lib().lbm3_last_error(hs[0]).decode())
+
+
+STEP_BATCH_STATIC_MAX_BYTES = 8 << 20  # LBM3_STEP_BATCH_STATIC_MAX_BYTES of include/lbm3.h
 
 
 def server_request_bytes(p):
