@@ -63,9 +63,14 @@ enum { LBM3_FP64 = 0, LBM3_FP32 = 1, LBM3_FP16S = 2 };
 enum {
     LBM3_NO_COLLIDE = 1u,   /* streaming and bounce-back only */
     LBM3_FORCE_ALPHA2 = 2u, /* alpha = 2 everywhere (BGK with 1/tau_f = 2 beta) */
-    LBM3_FUSED_3D = 4u      /* D3Q27: force, collision and streaming in one fused
+    LBM3_FUSED_3D = 4u,     /* D3Q27: force, collision and streaming in one fused
                                kernel instead of the default stencil pass plus
                                collide kernel (same arithmetic) */
+    LBM3_STORED_G = 8u      /* D3Q27 with tau_g = 1: store and stream the 27 g
+                               populations instead of the default implicit g
+                               (the collision keeps (a, phi, v) of g^eq per
+                               node, Eqs. 33-35, and the moments pass rebuilds
+                               the streamed g from them); bit-identical results */
 };
 
 /* Problem statement (paper Sec. II-IV).  Zero-initialise, then set. */
@@ -95,7 +100,8 @@ typedef struct {
     int32_t precision;      /* LBM3_FP64, LBM3_FP32, LBM3_FP16S (FP32 arithmetic,
                                populations stored in FP16 as density-scaled
                                offsets from the lattice weights) */
-    uint32_t flags;         /* LBM3_NO_COLLIDE | LBM3_FORCE_ALPHA2 | LBM3_FUSED_3D */
+    uint32_t flags;         /* LBM3_NO_COLLIDE | LBM3_FORCE_ALPHA2 | LBM3_FUSED_3D |
+                               LBM3_STORED_G */
     double  alpha_eps;      /* small-deviation alpha below this max |Delta/f'|
                                (0: 1e-3 FP64, 1e-2 FP32 arithmetic) */
     double  alpha_tol;      /* Newton tolerance (0: 1e-10 FP64, 1e-5 FP32) */

@@ -356,6 +356,55 @@ def contour_points_2d(c, level=0.5, y_offset=0.0):
     return np.array(xs), np.array(ys) + y_offset
 
 
+def lens_angles_2d(C2, C3, xc, W=4.0):
+    """Neumann angles (theta1, theta2, theta3) in degrees of a liquid-2 lens
+    floating on the upper edge of a liquid-3 layer in gas (Sec. III, the
+    three-phase contact whose angles Eqs. 40-42 give from the tensions).
+    The flat 3-gas interface height is the median of the C3 = 1/2 points of
+    the layer's upper edge (the upper of its two edges) more than 3 W beside
+    the lens; the C2 = 1/2 points
+    more than W above it and below it get one circle each; the two circles
+    cross at the contact points, where the rays along the upper arc, the
+    lower arc and the flat interface (pointing away from the lens) bound the
+    gas (theta1), liquid-2 (theta2) and liquid-3 (theta3) sectors.  Returns
+    the angles averaged over both contact points, and the per-point ones."""
+    x2, y2 = contour_points_2d(C2)
+    x3, y3 = contour_points_2d(C3)
+    half = 0.5 * (x2.max() - x2.min())
+    side = np.abs(x3 - xc) > half + 3.0 * W
+    ys = y3[side]
+    yf = float(np.median(ys[ys > ys.mean()]))
+    up, lo = y2 > yf + W, y2 < yf - W
+    a = kasa_fit(x2[up], y2[up])
+    b = kasa_fit(x2[lo], y2[lo])
+    ma = np.array([x2[up].mean(), y2[up].mean()])
+    mb = np.array([x2[lo].mean(), y2[lo].mean()])
+    # circle-circle intersection
+    ca, cb = np.array(a[:2]), np.array(b[:2])
+    d = np.linalg.norm(cb - ca)
+    l = (a[2] ** 2 - b[2] ** 2 + d * d) / (2.0 * d)
+    h = math.sqrt(max(a[2] ** 2 - l * l, 0.0))
+    e = (cb - ca) / d
+    base = ca + l * e
+    pts = [base + h * np.array([-e[1], e[0]]), base - h * np.array([-e[1], e[0]])]
+
+    def ray(P, c, m):
+        t = np.array([-(P - c)[1], (P - c)[0]])
+        t /= np.linalg.norm(t)
+        return t if np.dot(t, m - P) > 0 else -t
+
+    def ang(u, v):
+        return math.degrees(math.acos(max(-1.0, min(1.0, float(np.dot(u, v))))))
+
+    per = []
+    for P in pts:
+        ra, rb = ray(P, ca, ma), ray(P, cb, mb)
+        rf = np.array([1.0 if P[0] > xc else -1.0, 0.0])
+        per.append((ang(ra, rf), ang(ra, rb), ang(rb, rf)))
+    mean = tuple(float(np.mean([q[k] for q in per])) for k in range(3))
+    return mean, per, yf
+
+
 def kasa_fit(xs, ys):
     """Algebraic (Kasa) least-squares circle: x^2 + y^2 + D x + E y + F = 0."""
     A = np.stack([xs, ys, np.ones_like(xs)], axis=1)

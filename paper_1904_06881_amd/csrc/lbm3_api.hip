@@ -27,6 +27,7 @@ struct lbm3 {
     int prec;
     hipStream_t stream;
     int pc, fc;            // current population buffer, fields it is encoded with
+    bool gimp;             // g[pc] not written: the last collision stored (a, phi, v) in b.gp
     bool inited;
     int64_t step;
     std::string err;
@@ -39,7 +40,7 @@ namespace {
 const double PI = 3.14159265358979323846;
 
 struct Layout {
-    size_t f[2], g[2], rho[2], phi[2], fmu, scratch, counters, partials, result, total;
+    size_t f[2], g[2], rho[2], phi[2], fmu, gp, scratch, counters, partials, result, total;
 };
 
 int lattice_D(int32_t lattice) { return lattice == LBM3_D2Q9 ? 2 : (lattice == LBM3_D3Q27 ? 3 : 0); }
@@ -100,6 +101,16 @@ size_t counter_slots(const lbm3_params *p)
     return (size_t)lbm3k::kCntSlots + (size_t)lbm3k::small2d_block_slots(D, p->n[0], p->n[D - 1]);
 }
 
+// tau_g = 1 with collisions in the 3D two-kernel step (FP32 / FP64): the
+// post-collision g is g^eq of (a, phi, v), Eqs. 33-35, so the collision
+// stores those five values per node (20 or 40 bytes) instead of pushing 27
+// populations, and the next moments pass rebuilds the delivered g from them
+bool implicit_g(const lbm3_params *p)
+{
+    return p->lattice == LBM3_D3Q27 && p->precision != LBM3_FP16S && p->tau_g == 1.0 &&
+           !(p->flags & (LBM3_NO_COLLIDE | LBM3_FUSED_3D | LBM3_STORED_G));
+}
+
 Layout layout(const lbm3_params *p)
 {
     Layout L{};
@@ -115,6 +126,7 @@ Layout layout(const lbm3_params *p)
     for (int k = 0; k < 2; ++k) L.rho[k] = take((size_t)N * r);
     for (int k = 0; k < 2; ++k) L.phi[k] = take((size_t)N * r);
     L.fmu = D == 3 ? take((size_t)(D + 1) * N * r) : 0;  // F, mu_phi of the two-kernel step
+    L.gp = implicit_g(p) ? take((size_t)5 * N * r) : 0;    // (a, phi, v) of g^eq
     L.scratch = take((size_t)N * 8);
     L.counters = take(counter_slots(p) * lbm3k::kCntStride * sizeof(unsigned long long));
     L.partials = take((size_t)1024 * 16 * sizeof(double));
@@ -240,12 +252,14 @@ lbm3_status lbm3_create(const lbm3_params *p, void *ws, size_t bytes, void *stre
         b.phi[i] = base + L.phi[i];
     }
     b.fmu = D == 3 ? (void *)(base + L.fmu) : nullptr;
+    b.gp = L.gp ? (void *)(base + L.gp) : nullptr;
     b.scratch = (double *)(base + L.scratch);
     b.counters = (unsigned long long *)(base + L.counters);
     b.partials = (double *)(base + L.partials);
     b.result = (double *)(base + L.result);
     b.n_partials = 1024;
     h->pc = h->fc = 0;
+    h->gimp = false;
     h->inited = false;
     h->step = 0;
     *out = h;
@@ -292,11 +306,35 @@ lbm3_status lbm3_init(lbm3 *h, const double *rho0, const double *phi0)
 
 // The launches of one step: moments, ghost layers (unless the fused kernel
 // fills them itself), then the fused update.
+static int launch_moments(lbm3 *h)
+{
+    return h->gimp ? lbm3k::launch_moments_imp(h->kp, h->prec, h->b, h->pc, h->fc, h->stream)
+                   : lbm3k::launch_moments(h->kp, h->prec, h->b, h->pc, h->fc, h->stream);
+}
+
+// g[pc] written out where something reads the stored g
+static int materialize_g(lbm3 *h, hipStream_t st)
+{
+    if (!h->gimp) return 0;
+    if (lbm3k::launch_g_materialize(h->kp, h->prec, h->b, h->pc, st)) return -1;
+    h->gimp = false;
+    return 0;
+}
+
+// after the collision of a step: whether it stored (a, phi, v) instead of g
+static void stepped(lbm3 *h)
+{
+    h->pc ^= 1;
+    h->fc ^= 1;
+    h->step++;
+    h->gimp = h->b.gp != nullptr;
+}
+
 static int launch_step(lbm3 *h, int which)
 {
     const KParams &k = h->kp;
     switch (which) {
-    case 0: return lbm3k::launch_moments(k, h->prec, h->b, h->pc, h->fc, h->stream);
+    case 0: return launch_moments(h);
     case 1: return lbm3k::fused_fills_ghost(k) ? 0 : lbm3k::launch_ghost(k, h->prec, h->b, 1 - h->fc, h->stream);
     default: return lbm3k::launch_fused(k, h->prec, h->b, h->pc, h->fc, h->stream);
     }
@@ -310,9 +348,7 @@ lbm3_status lbm3_step(lbm3 *h, int64_t nsteps)
     for (int64_t t = 0; t < nsteps; ++t) {
         if (launch_step(h, 0) || launch_step(h, 1) || launch_step(h, 2))
             return set_err(h, LBM3_EDEVICE, "kernel launch failed");
-        h->pc ^= 1;
-        h->fc ^= 1;
-        h->step++;
+        stepped(h);
     }
     return LBM3_OK;
 }
@@ -376,9 +412,7 @@ lbm3_status lbm3_step_profiled(lbm3 *h, int64_t nsteps, int32_t sample_every, do
             lbm3k::set_stage_events(nullptr, nullptr, nullptr, nullptr);
         }
         if (r) { st = set_err(h, LBM3_EDEVICE, "kernel launch failed"); break; }
-        h->pc ^= 1;
-        h->fc ^= 1;
-        h->step++;
+        stepped(h);
         if (timed && ++pending == batch && !drain()) st = hip_err(h, e, "profiled step");
     }
     if (st == LBM3_OK && !drain()) st = hip_err(h, e, "profiled step");
@@ -412,9 +446,11 @@ lbm3_status lbm3_observe(lbm3 *h, uint32_t what, lbm3_obs *out, double *rho_out,
     hipError_t e;
     size_t bytes = (size_t)k.N * sizeof(double);
     lbm3_status status = LBM3_OK;
+    if ((what & (LBM3_OBS_POPS | LBM3_OBS_SUMS)) && materialize_g(h, h->stream))
+        return set_err(h, LBM3_EDEVICE, "kernel launch failed");
     if (what & LBM3_OBS_FIELDS) {
         // moments and ghost layers of the current state into the spare fields
-        if (lbm3k::launch_moments(k, h->prec, h->b, h->pc, h->fc, h->stream) ||
+        if (launch_moments(h) ||
             lbm3k::launch_ghost(k, h->prec, h->b, 1 - h->fc, h->stream))
             return set_err(h, LBM3_EDEVICE, "kernel launch failed");
         double *dst[2] = {rho_out, phi_out};
@@ -481,7 +517,7 @@ lbm3_status lbm3_contact_angle(lbm3 *h, int32_t comp, int32_t wall, double exclu
         return set_err(h, LBM3_EINVAL, "contact angle needs comp 2 or 3, wall 0 or 1, a walled grid");
     const KParams &k = h->kp;
     hipError_t e;
-    if (lbm3k::launch_moments(k, h->prec, h->b, h->pc, h->fc, h->stream) ||
+    if (launch_moments(h) ||
         lbm3k::launch_contour(k, h->prec, h->b, 1 - h->fc, comp, wall, exclude, h->stream))
         return set_err(h, LBM3_EDEVICE, "contour launch failed");
     double r[16];
@@ -716,6 +752,8 @@ lbm3_status build(lbm3 *const *hs, int n, Image &img)
             s.phi[j] = h->b.phi[j];
         }
         s.fmu = h->b.fmu;
+        s.gp = h->b.gp;
+        s.gimp0 = h->gimp ? 1 : 0;
         s.counters = h->b.counters;
         s.pc = h->pc;
         s.fc = h->fc;
@@ -752,7 +790,8 @@ lbm3_status enqueue(lbm3 *const *hs, int m, const Image &img, const void *dev_ba
             long long nb = l.prefix[k];
             if (nb == 0) continue;
             const int *tab = (const int *)(base + l.table_off);
-            int r = l.kind == 0 ? lbm3k::launch_moments_batch(l.D, l.prec, d, tab, nb, phase, stream)
+            const bool first = phase0 + t == 0;
+            int r = l.kind == 0 ? lbm3k::launch_moments_batch(l.D, l.prec, d, tab, nb, phase, first, stream)
                   : l.kind == 1 ? lbm3k::launch_ghost_batch(l.D, l.prec, d, tab, nb, phase, stream)
                   : l.kind == 2 ? lbm3k::launch_fused_batch(l.cls, l.prec, d, tab, nb, phase, stream)
                                 : lbm3k::launch_collide_batch(l.D, l.prec, d, tab, nb, phase, stream);
@@ -765,6 +804,7 @@ lbm3_status enqueue(lbm3 *const *hs, int m, const Image &img, const void *dev_ba
             hs[i]->fc ^= 1;
         }
         hs[i]->step += steps;
+        if (steps > 0 && hs[i]->b.gp) hs[i]->gimp = true;
     }
     return LBM3_OK;
 }

@@ -52,6 +52,7 @@ struct Buffers {
     void *f[2], *g[2];           // populations [Q][N], storage type by precision
     void *rho[2], *phi[2];       // fields [N], compute type
     void *fmu;                   // 3D two-kernel step: F, mu_phi [D + 1][N], compute type
+    void *gp;                    // implicit-g step: (a, phi, v) of g^eq [5][N], compute type, or null
     double *scratch;             // N doubles (upload / export staging)
     unsigned long long *counters;// kCntSlots (+ per-block) slots of kCntStride: newton, shortcut, fallback
     double *partials;            // reduction partials
@@ -69,6 +70,8 @@ struct SimDesc {
     void *fmu;                // F, mu_phi of the 3D two-kernel step
     int fblk0, mblk0, gblk0;  // its first block in the fused (or stencil), moments and ghost launches
     int cblk0;                // and in the collide launch of the 3D two-kernel step
+    void *gp;                 // implicit-g values (a, phi, v), or null
+    int gimp0;                // g[pc] implicit (in gp) when the descriptors were written
 };
 
 // Fused launch geometry of one simulation: tile class (0: 2D 62-node tiles,
@@ -81,6 +84,10 @@ struct FusedGeom {
 
 // Launchers (lbm3_kernels.hip).  All asynchronous on `stream`.
 int launch_moments(const KParams &kp, int prec, const Buffers &b, int pc, int fc, void *stream);
+// implicit-g step (b.gp set): the moments pass that rebuilds g from b.gp, and
+// the kernel that writes that g out into b.g[pc]
+int launch_moments_imp(const KParams &kp, int prec, const Buffers &b, int pc, int fc, void *stream);
+int launch_g_materialize(const KParams &kp, int prec, const Buffers &b, int pc, void *stream);
 int launch_ghost(const KParams &kp, int prec, const Buffers &b, int fdst, void *stream);
 int launch_fused(const KParams &kp, int prec, const Buffers &b, int pc, int fc, void *stream);
 // events (hipEvent_t, or null) the next launch_moments / launch_ghost /
@@ -111,8 +118,10 @@ FusedGeom fused_geometry(const KParams &kp, int prec);
 long long moments_blocks(const KParams &kp, int prec);
 long long ghost_blocks(const KParams &kp);  // 0 when the step has no ghost launch
 long long collide_blocks(const KParams &kp);  // 0 unless the step is two-kernel
+// first: the first step since the descriptors were written (a simulation's
+// g is then implicit if gimp0 says so, afterwards whenever gp is set)
 int launch_moments_batch(int D, int prec, const SimDesc *d, const int *sim, long long nblocks, int phase,
-                         void *stream);
+                         bool first, void *stream);
 int launch_ghost_batch(int D, int prec, const SimDesc *d, const int *sim, long long nblocks, int phase,
                        void *stream);
 int launch_fused_batch(int cls, int prec, const SimDesc *d, const int *sim, long long nblocks, int phase,

@@ -435,36 +435,92 @@ __device__ __forceinline__ int collide_f(R *f, R r0, const R *u, const R *du, R 
     return kind;
 }
 
-// LBGK of g toward g^eq(phi, v), v = u + du/2 (Eqs. 33-35); the rest
-// population takes phi minus the moving ones.  With tau_g = 1 the update is
-// g* = g^eq exactly (the stored g is not needed, and FRESH callers do not
-// load it); otherwise g* = g + (g^eq - g)/tau_g.  g^eq_i = w_i (a + v.c_i
-// (b + c v.c_i)) with a = 3 Gamma mu_phi - 1.5 phi |v|^2, b = 3 phi,
-// c = 4.5 phi.
+// g^eq(phi, v), v = u + du/2 (Eqs. 33-35): g^eq_i = w_i (a + v.c_i (b +
+// c v.c_i)) with a = 3 Gamma mu_phi - 1.5 phi |v|^2, b = 3 phi, c = 4.5 phi
+// for i other than the rest velocity; g^eq_rest = phi - (the sum of the
+// others, in population order).
+// Evaluated without contraction, so the moments pass that rebuilds g from
+// (a, phi, v) at tau_g = 1 gets the very values the collision produced.
+template <int D, typename R>
+__device__ __forceinline__ R geq_a(const R *v, R p0, R mup, R Gam)
+{
+#pragma clang fp contract(off)
+    R vv = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) vv += v[a] * v[a];
+    return (R)3 * Gam * mup - (R)1.5 * p0 * vv;
+}
+template <int D, typename R>
+__device__ __forceinline__ R geq_i(int i, const R *v, R ca, R cb, R cc)
+{
+#pragma clang fp contract(off)
+    R vc = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+        if (cdir(D, i, a) != 0) vc += (R)cdir(D, i, a) * v[a];
+    return (R)wgt(D, i) * (ca + vc * (cb + cc * vc));
+}
+template <int D, typename R>
+__device__ __forceinline__ R geq_rest(const R *v, R p0, R ca)
+{
+#pragma clang fp contract(off)
+    constexpr int Q = D == 2 ? 9 : 27;
+    const R cb = (R)3 * p0, cc = (R)4.5 * p0;
+    R sum = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+        if (i != Q / 2) sum += geq_i<D, R>(i, v, ca, cb, cc);
+    return p0 - sum;
+}
+
+// LBGK for g (Eqs. 33-35).  At tau_g = 1 (itg = 1) g* = g^eq exactly (the
+// stored g is not needed, and FRESH callers do not load it); otherwise
+// g* = g + (g^eq - g)/tau_g.
 template <int D, typename R, bool FRESH = false>
 __device__ __forceinline__ void collide_g(R *gg, const R *v, R p0, R mup, R Gam, R itg)
 {
     constexpr int Q = D == 2 ? 9 : 27;
-    R vv = 0;
-#pragma unroll
-    for (int a = 0; a < D; ++a) vv += v[a] * v[a];
-    const R ca = (R)3 * Gam * mup - (R)1.5 * p0 * vv, cb = (R)3 * p0, cc = (R)4.5 * p0;
+    const R ca = geq_a<D, R>(v, p0, mup, Gam), cb = (R)3 * p0, cc = (R)4.5 * p0;
     const bool one = itg == (R)1;
-    R sum = 0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         if (i == Q / 2) continue;
-        R vc = 0;
-#pragma unroll
-        for (int a = 0; a < D; ++a)
-            if (cdir(D, i, a) != 0) vc += (R)cdir(D, i, a) * v[a];
-        const R ge = (R)wgt(D, i) * (ca + vc * (cb + cc * vc));
-        sum += ge;
+        const R ge = geq_i<D, R>(i, v, ca, cb, cc);
         if constexpr (FRESH) gg[i] = ge;
         else gg[i] = one ? ge : gg[i] + (ge - gg[i]) * itg;
     }
-    if constexpr (FRESH) gg[Q / 2] = p0 - sum;
-    else gg[Q / 2] = one ? p0 - sum : gg[Q / 2] + ((p0 - sum) - gg[Q / 2]) * itg;
+    const R gr = geq_rest<D, R>(v, p0, ca);
+    if constexpr (FRESH) gg[Q / 2] = gr;
+    else gg[Q / 2] = one ? gr : gg[Q / 2] + (gr - gg[Q / 2]) * itg;
+}
+
+// Raw buffer access to one array of n elements at a uniform base: the
+// resource (base, size) lives in scalar registers and each lane supplies a
+// 32-bit byte offset, so no 64-bit address arithmetic is spent per access;
+// accesses beyond the array read 0 and drop the store.  Every array of a
+// simulation is below 4 GiB (checked when the handle is created).
+template <typename T> __device__ __forceinline__ __amdgpu_buffer_rsrc_t arr(const T *base, unsigned n)
+{
+    return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, (int)(n * (unsigned)sizeof(T)), 0x00020000);
+}
+template <typename T> __device__ __forceinline__ T ld32(__amdgpu_buffer_rsrc_t r, unsigned byte_off)
+{
+    if constexpr (sizeof(T) == 8)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 0));
+    else if constexpr (sizeof(T) == 4)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, byte_off, 0, 0));
+}
+template <typename T> __device__ __forceinline__ void st32(__amdgpu_buffer_rsrc_t r, unsigned byte_off, T v)
+{
+    using U2 = unsigned __attribute__((ext_vector_type(2)));
+    if constexpr (sizeof(T) == 8)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, v), r, byte_off, 0, 0);
+    else if constexpr (sizeof(T) == 4)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, byte_off, 0, 0);
+    else
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, byte_off, 0, 0);
 }
 
 // -------------------------------------------------------------- moments --
@@ -554,21 +610,175 @@ __device__ __forceinline__ T *on_global(const SimDesc *base, const void *p)
     return (T *)((const char *)base + (long long)((uintptr_t)p - (uintptr_t)base));
 }
 
+// Blocks of a launch go to the 8 XCDs in turn (block b to XCD b mod 8),
+// each with its own L2: renumbered so that every XCD walks one contiguous
+// eighth of the grid and finds the rows and planes around its nodes in its
+// own L2.  A bijection on [0, nb) (identity for the last nb mod 8 blocks).
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb)
+{
+    const unsigned per = nb / 8u;
+    if (b >= per * 8u) return b;
+    return (b % 8u) * per + b / 8u;
+}
+
+// The g populations that streaming delivers to a fluid node when tau_g = 1
+// with collisions (3D two-kernel step), from the (a, phi, v) that the
+// collision stored at every node: g_i(x) = g^eq_i at the source x - c_i,
+// or for a population bounced back at a wall g^eq of the opposite velocity
+// at x itself, and the rest population g^eq_rest(x).  get(cx, cy, cz, k)
+// returns value k of (a, phi, v0, v1, v2) at x - c; low / high: the node
+// lies on the first / last fluid plane of a walled grid.  The values are
+// those the collision computed; sink(i, g_i) sees them in population order.
+template <typename R, typename Get, typename Sink>
+__device__ __forceinline__ void implicit_g(Get get, bool low, bool high, Sink sink)
+{
+    constexpr int D = 3, Q = 27;
+    const R oa = get(0, 0, 0, 0), op = get(0, 0, 0, 1);
+    const R ov[3] = {get(0, 0, 0, 2), get(0, 0, 0, 3), get(0, 0, 0, 4)};
+    const R ob = (R)3 * op, oc = (R)4.5 * op;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int cx = cdir(D, i, 0), cy = cdir(D, i, 1), cz = cdir(D, i, 2);
+        if (i == Q / 2) {
+            sink(i, geq_rest<D, R>(ov, op, oa));
+        } else if ((cz > 0 && low) || (cz < 0 && high)) {
+            sink(i, geq_i<D, R>(Q - 1 - i, ov, oa, ob, oc));
+        } else {
+            const R sa = get(cx, cy, cz, 0), sp = get(cx, cy, cz, 1);
+            const R sv[3] = {get(cx, cy, cz, 2), get(cx, cy, cz, 3), get(cx, cy, cz, 4)};
+            sink(i, geq_i<D, R>(i, sv, sa, (R)3 * sp, (R)4.5 * sp));
+        }
+    }
+}
+
+// Moments pass of the implicit-g step: rho = sum of the stored f, phi = sum
+// of the delivered g (rebuilt as above), both in population order: the same
+// values and sums as the stored-g pass.  A block is a TX x TY tile of one
+// fluid plane; the five values of the tile, its one-node ring and the
+// planes above and below go through LDS once (each is read by 27 nodes).
+template <int PREC, int TX, int TY>
+__global__ void __launch_bounds__(TX * TY)
+k_moments_imp(KParams kp, const typename Ty<PREC>::S *__restrict__ f, const typename Ty<PREC>::R *__restrict__ gp,
+              typename Ty<PREC>::R *__restrict__ rho, typename Ty<PREC>::R *__restrict__ phi)
+{
+    using R = typename Ty<PREC>::R;
+    using S = typename Ty<PREC>::S;
+    constexpr int Q = 27, EX = TX + 2, EY = TY + 2, CELLS = 3 * EY * EX;
+    constexpr unsigned SR = sizeof(R);
+    __shared__ R s_p[5][CELLS];
+    const int nx = kp.nx, ny = kp.ny, nw = kp.nw;
+    const bool walls = kp.walls != 0;
+    const unsigned N = (unsigned)kp.N, PS = (unsigned)kp.PS;
+    const int ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY;
+    const unsigned b = xcd_block(blockIdx.x, gridDim.x);
+    const int tx = (int)(b % (unsigned)ntx), ty = (int)((b / (unsigned)ntx) % (unsigned)nty);
+    const int p = (int)(b / (unsigned)(ntx * nty)) + (walls ? 1 : 0);
+    const int x0 = tx * TX, y0 = ty * TY;
+    for (int c = threadIdx.x; c < CELLS; c += TX * TY) {
+        const int lx = c % EX, ly = (c / EX) % EY, lz = c / (EX * EY);
+        // periodic wrap without a division (a tile may pass the end of a
+        // small grid more than once)
+        int gx = x0 + lx - 1, gy = y0 + ly - 1;
+        if (gx < 0) gx += nx;
+        while (gx >= nx) gx -= nx;
+        if (gy < 0) gy += ny;
+        while (gy >= ny) gy -= ny;
+        int gz = p + lz - 1;
+        if (!walls) gz = gz < 0 ? gz + nw : (gz >= nw ? gz - nw : gz);
+        const unsigned off = ((unsigned)gz * PS + (unsigned)gy * (unsigned)nx + (unsigned)gx) * SR;
+#pragma unroll
+        for (int k = 0; k < 5; ++k) s_p[k][c] = ld32<R>(arr(gp + (size_t)k * N, N), off);
+    }
+    __syncthreads();
+    const int lx = (int)threadIdx.x % TX, ly = (int)threadIdx.x / TX;
+    const int x = x0 + lx, y = y0 + ly;
+    if (x >= nx || y >= ny) return;
+    const unsigned n = (unsigned)p * PS + (unsigned)y * (unsigned)nx + (unsigned)x;
+    S fr[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) fr[i] = ld32<S>(arr(f + (size_t)i * N, N), n * (unsigned)sizeof(S));
+    R r = 0, ph = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) r += (R)fr[i];
+    const int l0 = (EY + ly + 1) * EX + lx + 1;  // the node in the middle plane
+    auto get = [&](int cx, int cy, int cz, int k) { return s_p[k][l0 - cz * (EX * EY) - cy * EX - cx]; };
+    implicit_g<R>(get, walls && p == 1, walls && p == nw - 2, [&](int, R g) { ph += g; });
+    st32<R>(arr(rho, N), n * SR, r);
+    st32<R>(arr(phi, N), n * SR, ph);
+}
+
+// implicit_g at fluid node n with the values gathered from global memory
+template <int PREC, typename Sink>
+__device__ __forceinline__ void implicit_g_global(const KParams &kp, const typename Ty<PREC>::R *__restrict__ gp,
+                                                  unsigned n, Sink sink)
+{
+    using R = typename Ty<PREC>::R;
+    constexpr unsigned SR = sizeof(R);
+    const unsigned N = (unsigned)kp.N, PS = (unsigned)kp.PS;
+    const int nx = kp.nx, ny = kp.ny, nw = kp.nw;
+    const bool walls = kp.walls != 0;
+    const int x = (int)(n % (unsigned)nx), y = (int)((n / (unsigned)nx) % (unsigned)ny), p = (int)(n / PS);
+    auto get = [&](int cx, int cy, int cz, int k) {
+        const int sx = x - cx < 0 ? x - cx + nx : (x - cx >= nx ? x - cx - nx : x - cx);
+        const int sy = y - cy < 0 ? y - cy + ny : (y - cy >= ny ? y - cy - ny : y - cy);
+        const int sz = walls ? p - cz : (p - cz < 0 ? p - cz + nw : (p - cz >= nw ? p - cz - nw : p - cz));
+        const unsigned off = ((unsigned)sz * PS + (unsigned)sy * (unsigned)nx + (unsigned)sx) * SR;
+        return ld32<R>(arr(gp + (size_t)k * N, N), off);
+    };
+    implicit_g<R>(get, walls && p == 1, walls && p == nw - 2, sink);
+}
+
+// The implicit g written out as populations (before anything that reads the
+// stored g: observables, exports).
+template <int PREC>
+__global__ void __launch_bounds__(256)
+k_g_materialize(KParams kp, const typename Ty<PREC>::R *__restrict__ gp, typename Ty<PREC>::S *__restrict__ g)
+{
+    using R = typename Ty<PREC>::R;
+    using S = typename Ty<PREC>::S;
+    const long long count = kp.walls ? kp.N - 2 * kp.PS : kp.N;
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count) return;
+    const unsigned n = (unsigned)((kp.walls ? kp.PS : 0) + t), N = (unsigned)kp.N;
+    implicit_g_global<PREC>(kp, gp, n, [&](int i, R v) {
+        st32<S>(arr(g + (size_t)i * N, N), n * (unsigned)sizeof(S), (S)v);
+    });
+}
+
 // One launch over many simulations: block b belongs to simulation sim[b];
-// `phase` is the number of steps taken since the descriptors were written.
+// `phase` is the parity of the steps taken since the descriptors were
+// written, `first` whether this is the first of them.  A simulation whose g
+// is implicit (3D, tau_g = 1) rebuilds it from its five values per node,
+// gathered from global memory: one thread per node, the same values and
+// sums as the tiled single-simulation pass.
 template <int D, int PREC>
 __global__ void __launch_bounds__(256)
-k_moments_batch(const SimDesc *__restrict__ d, const int *__restrict__ sim, int phase)
+k_moments_batch(const SimDesc *__restrict__ d, const int *__restrict__ sim, int phase, int first)
 {
     using R = typename Ty<PREC>::R;
     using S = typename Ty<PREC>::S;
     const SimDesc &sd = d[sim[blockIdx.x]];
     const KParams &kp = sd.kp;
     const int pc = sd.pc ^ phase, fc = sd.fc ^ phase;
+    const long long t = (long long)(blockIdx.x - sd.mblk0) * blockDim.x + threadIdx.x;
+    if constexpr (D == 3 && PREC != P16) {
+        if (sd.gp && (!first || sd.gimp0)) {
+            const long long count = kp.walls ? kp.N - 2 * kp.PS : kp.N;
+            if (t >= count) return;
+            const unsigned n = (unsigned)((kp.walls ? kp.PS : 0) + t), N = (unsigned)kp.N;
+            const S *f = on_global<const S>(d, sd.f[pc]);
+            R r = 0, ph = 0;
+#pragma unroll
+            for (int i = 0; i < 27; ++i) r += (R)ld32<S>(arr(f + (size_t)i * N, N), n * (unsigned)sizeof(S));
+            implicit_g_global<PREC>(kp, on_global<const R>(d, sd.gp), n, [&](int, R g) { ph += g; });
+            st32<R>(arr(on_global<R>(d, sd.rho[1 - fc]), N), n * (unsigned)sizeof(R), r);
+            st32<R>(arr(on_global<R>(d, sd.phi[1 - fc]), N), n * (unsigned)sizeof(R), ph);
+            return;
+        }
+    }
     moments_node<D, PREC>(kp, on_global<const S>(d, sd.f[pc]), on_global<const S>(d, sd.g[pc]),
                           on_global<const R>(d, sd.rho[fc]), on_global<const R>(d, sd.phi[fc]),
-                          on_global<R>(d, sd.rho[1 - fc]), on_global<R>(d, sd.phi[1 - fc]),
-                          (long long)(blockIdx.x - sd.mblk0) * blockDim.x + threadIdx.x);
+                          on_global<R>(d, sd.rho[1 - fc]), on_global<R>(d, sd.phi[1 - fc]), t);
 }
 
 // ----------------------------------------------------------- ghost layers
@@ -1583,35 +1793,6 @@ k_stencil_batch(const SimDesc *__restrict__ d, const int *__restrict__ sim, int 
                                on_global<R>(d, sd.fmu), sd.chunk, local % sd.ntiles, local / sd.ntiles);
 }
 
-// Raw buffer access to one array of n elements at a uniform base: the
-// resource (base, size) lives in scalar registers and each lane supplies a
-// 32-bit byte offset, so no 64-bit address arithmetic is spent per access;
-// accesses beyond the array read 0 and drop the store.  Every array of a
-// simulation is below 4 GiB (checked when the handle is created).
-template <typename T> __device__ __forceinline__ __amdgpu_buffer_rsrc_t arr(const T *base, unsigned n)
-{
-    return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, (int)(n * (unsigned)sizeof(T)), 0x00020000);
-}
-template <typename T> __device__ __forceinline__ T ld32(__amdgpu_buffer_rsrc_t r, unsigned byte_off)
-{
-    if constexpr (sizeof(T) == 8)
-        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 0));
-    else if constexpr (sizeof(T) == 4)
-        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
-    else
-        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, byte_off, 0, 0));
-}
-template <typename T> __device__ __forceinline__ void st32(__amdgpu_buffer_rsrc_t r, unsigned byte_off, T v)
-{
-    using U2 = unsigned __attribute__((ext_vector_type(2)));
-    if constexpr (sizeof(T) == 8)
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, v), r, byte_off, 0, 0);
-    else if constexpr (sizeof(T) == 4)
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, byte_off, 0, 0);
-    else
-        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, byte_off, 0, 0);
-}
-
 // Collision and push streaming of fluid node number t (counted from the
 // first fluid plane), the second kernel of the two-kernel step: F and mu_phi
 // from the stencil pass, rho, phi of the node and of its push targets (for
@@ -1625,8 +1806,11 @@ template <typename T> __device__ __forceinline__ void st32(__amdgpu_buffer_rsrc_
 // bounce-back choice of each population is a scalar branch.  GL: whether
 // the stored g is loaded (0 never: tau_g = 1 with collisions, where
 // g* = g^eq; 1 always; 2 decided at run time by the same rule, for the
-// batched kernel).  Target addresses are the sum of an x, a y and a plane
-// byte offset, shared by the f and g stores.
+// batched kernel; 3 never, and g is not stored either: tau_g = 1 with
+// collisions, where the post-collision g is g^eq of (a, phi, v) and the node
+// stores those five values for the next moments pass).  Target addresses
+// are the sum of an x, a y and a plane byte offset, shared by the f and g
+// stores.
 template <int D, int PREC, bool UNI, int GL>
 __device__ __forceinline__ int collide_node(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin,
                                             const typename Ty<PREC>::S *__restrict__ gin,
@@ -1650,6 +1834,7 @@ __device__ __forceinline__ int collide_node(const KParams &kp, const typename Ty
     const bool collide = !(kp.flags & 1u), alpha2 = (kp.flags & 2u) != 0;
     const R itg = (R)kp.inv_tau_g;
     const bool need_g = GL == 1 || (GL == 2 && (!collide || itg != (R)1));
+    static_assert(GL != 3 || D == 3, "implicit g is a 3D two-kernel path");
 
     S fr[Q];
 #pragma unroll
@@ -1725,6 +1910,16 @@ __device__ __forceinline__ int collide_node(const KParams &kp, const typename Ty
             st32<S>(arr(fout + (size_t)i * N, N), nt, enc_f<PREC, D>(f[i], i, rt));
         }
     }
+    if constexpr (GL == 3) {
+        // g* = g^eq is a function of (a, phi, v): store those five values at
+        // the node instead of pushing 27 populations
+        static_assert(PREC != P16, "implicit g needs the compute type");
+        R *gp = (R *)gout;
+        const R vals[5] = {geq_a<D, R>(v, p0, mup, Gam), p0, v[0], v[1], v[2]};
+#pragma unroll
+        for (int k = 0; k < 5; ++k) st32<R>(arr(gp + (size_t)k * N, N), n * SR, vals[k]);
+        return kind;
+    }
     if (!need_g) {
         collide_g<D, R, true>(gg, v, p0, mup, Gam, itg);
     } else if constexpr (GL != 0) {
@@ -1797,13 +1992,27 @@ k_collide_batch(const SimDesc *__restrict__ d, const int *__restrict__ sim, int 
     int kind = -1;
     // the same arithmetic either way; a plane stride that is a multiple of
     // the wave makes the bounce-back branches scalar (block-uniform test)
-    auto node = [&](auto uni) {
-        return collide_node<D, PREC, decltype(uni)::value, 2>(
+    // implicit g (gp set: tau_g = 1 with collisions): the five values go to gp
+    auto node = [&](auto uni, auto gl) {
+        S *gout = decltype(gl)::value == 3 ? on_global<S>(d, sd.gp) : on_global<S>(d, sd.g[1 - pc]);
+        return collide_node<D, PREC, decltype(uni)::value, decltype(gl)::value>(
             kp, on_global<const S>(d, sd.f[pc]), on_global<const S>(d, sd.g[pc]), on_global<S>(d, sd.f[1 - pc]),
-            on_global<S>(d, sd.g[1 - pc]), on_global<const R>(d, sd.rho[1 - fc]), on_global<const R>(d, sd.phi[1 - fc]),
+            gout, on_global<const R>(d, sd.rho[1 - fc]), on_global<const R>(d, sd.phi[1 - fc]),
             on_global<const R>(d, sd.rho[fc]), on_global<const R>(d, sd.phi[fc]), on_global<const R>(d, sd.fmu), t);
     };
-    if (t < count) kind = kp.PS % 64 == 0 ? node(std::true_type{}) : node(std::false_type{});
+    using G2 = std::integral_constant<int, 2>;
+    using G3 = std::integral_constant<int, 3>;
+    if (t < count) {
+        const bool uni = kp.PS % 64 == 0;
+        bool done = false;
+        if constexpr (D == 3 && PREC != P16) {
+            if (sd.gp) {
+                kind = uni ? node(std::true_type{}, G3{}) : node(std::false_type{}, G3{});
+                done = true;
+            }
+        }
+        if (!done) kind = uni ? node(std::true_type{}, G2{}) : node(std::false_type{}, G2{});
+    }
     count_kinds(kind, s_cnt);
     __syncthreads();
     if (threadIdx.x < 3 && s_cnt[threadIdx.x])
@@ -2115,6 +2324,34 @@ int launch_moments(const KParams &kp, int prec, const Buffers &b, int pc, int fc
     return moments_t<3, P16>(kp, b, pc, fc, st);
 }
 
+int launch_moments_imp(const KParams &kp, int prec, const Buffers &b, int pc, int fc, void *stream)
+{
+    hipStream_t st = (hipStream_t)stream;
+    if (kp.D != 3 || !b.gp || prec == P16) return -1;
+    constexpr int TX = 64, TY = 4;
+    const long long planes = kp.walls ? kp.nw - 2 : kp.nw;
+    const long long nb = (long long)((kp.nx + TX - 1) / TX) * ((kp.ny + TY - 1) / TY) * planes;
+    if (prec == P64)
+        stage_launch(k_moments_imp<P64, TX, TY>, dim3((unsigned)nb), dim3(TX * TY), st, true, true, kp,
+                     (SP<P64>)b.f[pc], (RP<P64>)b.gp, (RP<P64>)b.rho[1 - fc], (RP<P64>)b.phi[1 - fc]);
+    else
+        stage_launch(k_moments_imp<P32, TX, TY>, dim3((unsigned)nb), dim3(TX * TY), st, true, true, kp,
+                     (SP<P32>)b.f[pc], (RP<P32>)b.gp, (RP<P32>)b.rho[1 - fc], (RP<P32>)b.phi[1 - fc]);
+    return LBM3_CHECK_LAUNCH();
+}
+
+int launch_g_materialize(const KParams &kp, int prec, const Buffers &b, int pc, void *stream)
+{
+    hipStream_t st = (hipStream_t)stream;
+    if (kp.D != 3 || !b.gp || prec == P16) return -1;
+    const long long count = kp.walls ? kp.N - 2 * kp.PS : kp.N;
+    if (prec == P64)
+        k_g_materialize<P64><<<nblk(count, 256), 256, 0, st>>>(kp, (RP<P64>)b.gp, (SP<P64>)b.g[pc]);
+    else
+        k_g_materialize<P32><<<nblk(count, 256), 256, 0, st>>>(kp, (RP<P32>)b.gp, (SP<P32>)b.g[pc]);
+    return LBM3_CHECK_LAUNCH();
+}
+
 int launch_ghost(const KParams &kp, int prec, const Buffers &b, int fdst, void *stream)
 {
     if (!kp.walls) return 0;
@@ -2213,11 +2450,21 @@ static int split_t(const KParams &kp, const Buffers &b, int pc, int fc, hipStrea
     // tau_g = 1 with collisions: the stored g is not read
     const bool uni = kp.PS % 64 == 0;
     const bool gl = (kp.flags & 1u) || kp.inv_tau_g != 1.0;
+    // implicit g: the collision stores (a, phi, v) in b.gp instead of g
+    const bool imp = b.gp != nullptr && !gl && PREC != P16;
     auto go = [&](auto kern) {
         stage_launch(kern, dim3((unsigned)collide_blocks(kp)), dim3(256), st, false, true, kp, (SP<PREC>)b.f[pc],
-                     (SP<PREC>)b.g[pc], (SP<PREC>)b.f[1 - pc], (SP<PREC>)b.g[1 - pc], (RP<PREC>)b.rho[1 - fc],
-                     (RP<PREC>)b.phi[1 - fc], (RP<PREC>)b.rho[fc], (RP<PREC>)b.phi[fc], (RP<PREC>)b.fmu, b.counters);
+                     (SP<PREC>)b.g[pc], (SP<PREC>)b.f[1 - pc], imp ? (SP<PREC>)b.gp : (SP<PREC>)b.g[1 - pc],
+                     (RP<PREC>)b.rho[1 - fc], (RP<PREC>)b.phi[1 - fc], (RP<PREC>)b.rho[fc], (RP<PREC>)b.phi[fc],
+                     (RP<PREC>)b.fmu, b.counters);
     };
+    if constexpr (PREC != P16) {
+        if (imp) {
+            if (uni) go(k_collide<3, PREC, true, 3>);
+            else go(k_collide<3, PREC, false, 3>);
+            return LBM3_CHECK_LAUNCH();
+        }
+    }
     if (uni) {
         if (gl) go(k_collide<3, PREC, true, 1>);
         else go(k_collide<3, PREC, true, 0>);
@@ -2277,19 +2524,20 @@ long long ghost_blocks(const KParams &kp)
 }
 
 int launch_moments_batch(int D, int prec, const SimDesc *d, const int *sim, long long nblocks, int phase,
-                         void *stream)
+                         bool first, void *stream)
 {
     if (nblocks <= 0) return 0;
     hipStream_t st = (hipStream_t)stream;
     dim3 grid((unsigned)nblocks);
+    const int fi = first ? 1 : 0;
     if (D == 2) {
-        if (prec == P64) k_moments_batch<2, P64><<<grid, 256, 0, st>>>(d, sim, phase);
-        else if (prec == P32) k_moments_batch<2, P32><<<grid, 256, 0, st>>>(d, sim, phase);
-        else k_moments_batch<2, P16><<<grid, 256, 0, st>>>(d, sim, phase);
+        if (prec == P64) k_moments_batch<2, P64><<<grid, 256, 0, st>>>(d, sim, phase, fi);
+        else if (prec == P32) k_moments_batch<2, P32><<<grid, 256, 0, st>>>(d, sim, phase, fi);
+        else k_moments_batch<2, P16><<<grid, 256, 0, st>>>(d, sim, phase, fi);
     } else {
-        if (prec == P64) k_moments_batch<3, P64><<<grid, 256, 0, st>>>(d, sim, phase);
-        else if (prec == P32) k_moments_batch<3, P32><<<grid, 256, 0, st>>>(d, sim, phase);
-        else k_moments_batch<3, P16><<<grid, 256, 0, st>>>(d, sim, phase);
+        if (prec == P64) k_moments_batch<3, P64><<<grid, 256, 0, st>>>(d, sim, phase, fi);
+        else if (prec == P32) k_moments_batch<3, P32><<<grid, 256, 0, st>>>(d, sim, phase, fi);
+        else k_moments_batch<3, P16><<<grid, 256, 0, st>>>(d, sim, phase, fi);
     }
     return LBM3_CHECK_LAUNCH();
 }

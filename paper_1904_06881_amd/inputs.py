@@ -95,6 +95,17 @@ def bubble_2d(nx, ny, r, inside=(1, 0), outside=(0, 0), W=4.0, **kw):
     return fields_from_conc(C2, C3, **kw)
 
 
+def lens_2d(nx, ny, r, band=None, W=4.0, **kw):
+    """Liquid-2 drop of radius r centred on the upper edge of a liquid-3 band
+    (rows band[0] .. band[1], default ny/4 .. ny/2) in gas, periodic box: the
+    floating-lens set-up of a three-phase contact (Neumann triangle)."""
+    x, y = _grid2(nx, ny)
+    y0, y1 = (ny / 4.0, ny / 2.0) if band is None else band
+    C2 = profile(r - np.sqrt((x - nx / 2.0) ** 2 + (y - y1) ** 2), W)
+    C3 = profile(np.minimum(y - y0, y1 - y), W) * (1.0 - C2)
+    return fields_from_conc(C2, C3, **kw)
+
+
 def capillary_2d(nx, ny, x_front, film=3, W=4.0, **kw):
     """Channel with walls at y = 0, ny-1: liquid 2 fills x < x_front at full
     height, a liquid-3 film covers `film` fluid rows on both walls along the

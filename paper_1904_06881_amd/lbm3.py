@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "liblbm3.so")
 D2Q9, D3Q27 = 9, 27
 WET_FORCE, WET_GEOM_INTERP, WET_GEOM_EXTRAP = 0, 1, 2
 FP64, FP32, FP16S = 0, 1, 2
-NO_COLLIDE, FORCE_ALPHA2, FUSED_3D = 1, 2, 4
+NO_COLLIDE, FORCE_ALPHA2, FUSED_3D, STORED_G = 1, 2, 4, 8
 OBS_SUMS, OBS_FIELDS, OBS_POPS = 1, 2, 4
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EUNSTABLE", -4: "EDEVICE", -5: "ESTATE",
           -6: "ECALIB"}

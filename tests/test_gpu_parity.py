@@ -127,7 +127,7 @@ def test_fp64_d3q27(wetting):
     assert err <= 1e-11
 
 
-@pytest.mark.parametrize("prec,tol", [(L.FP64, 1e-13), (L.FP32, 1e-5), (L.FP16S, 2e-3)])
+@pytest.mark.parametrize("prec,tol", [(L.FP64, 1e-13), (L.FP32, 2e-5), (L.FP16S, 2e-3)])
 @pytest.mark.parametrize("wetting", [L.WET_GEOM_INTERP, L.WET_FORCE, "periodic"])
 def test_two_kernel_3d_step_matches_fused(prec, tol, wetting):
     """D3Q27: the default step (stencil pass, then one thread per node for
@@ -138,7 +138,9 @@ def test_two_kernel_3d_step_matches_fused(prec, tol, wetting):
     with the oracle (max-abs C_k <= 1e-11).  The stencil pass factors the
     isotropic stencils along the axes and the compiler may fuse different
     products into FMAs, so the two kernels agree to the growth of a few
-    roundings per step over 30 steps, not bit for bit."""
+    roundings per step over 30 steps, not bit for bit: in FP32 2e-5, about
+    40 units in the last place of the largest field value (|phi| up to
+    chi = 5; measured 1.0e-5)."""
     nx, ny, nz = 37, 22, 18
     walls = wetting != "periodic"
     if walls:
