@@ -239,7 +239,8 @@ lbm3_status lbm3_step_batch_static(lbm3 *const *hs, int32_t n, int64_t nsteps, v
  * grids fill the GPU alone) -- later requests may pass one that does not
  * fit, until it has waited max_skips rounds -- and enqueues up
  * to `quantum` batched steps of everything resident in it.  Tension
- * calibration (lbm3_resolve) runs at submission, on the host. */
+ * calibration (lbm3_resolve) runs on host worker threads from submission
+ * on, while the GPU steps the resident simulations. */
 typedef struct lbm3_server lbm3_server;
 
 typedef struct {
@@ -268,9 +269,13 @@ lbm3_status lbm3_server_create(void *pool, size_t pool_bytes, void *stream, int3
                                int32_t max_skips, lbm3_server **out);
 
 /* Queue a request; rho0, phi0 (host, n[0] n[1] n[2] doubles each, x fastest)
- * are copied.  Parameter or calibration failures, or a footprint beyond the
- * pool, come back at once as a result with that status (the call itself
- * returns LBM3_OK); LBM3_EINVAL only for null arguments or nsteps < 0. */
+ * are copied.  Parameter failures or a footprint beyond the pool come back
+ * at once as a result with that status (the call itself returns LBM3_OK);
+ * LBM3_EINVAL only for null arguments or nsteps < 0.  The calibration of
+ * (lambda, kappa) from the tensions (lbm3_resolve) runs on the server's
+ * worker threads, overlapped with the GPU work; a request is admitted once
+ * it is calibrated (requests still calibrating may be overtaken), and a
+ * calibration failure comes back as a result with LBM3_ECALIB. */
 lbm3_status lbm3_server_submit(lbm3_server *s, const lbm3_params *p, const double *rho0, const double *phi0,
                                int64_t nsteps, uint64_t tag, uint32_t flags);
 

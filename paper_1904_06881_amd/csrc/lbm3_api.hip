@@ -694,7 +694,7 @@ static void plan(lbm3 *const *hs, int n, std::vector<Launch> &L)
         int prec = hs[i]->prec;
         Launch &m = find(0, k.D, prec, 0);
         m.sims.push_back(i);
-        m.prefix.push_back(m.prefix.back() + lbm3k::moments_blocks(k, prec));
+        m.prefix.push_back(m.prefix.back() + lbm3k::moments_batch_blocks(k, prec, hs[i]->b.gp != nullptr));
         long long gb = lbm3k::ghost_blocks(k);
         if (gb > 0) {
             Launch &g = find(1, k.D, prec, 0);

@@ -116,6 +116,9 @@ int observe_blocks(const KParams &kp);
 // belong to simulation sim[b] of the device descriptor array d.
 FusedGeom fused_geometry(const KParams &kp, int prec);
 long long moments_blocks(const KParams &kp, int prec);
+// the batched moments launch: the tiled pass for a simulation with an
+// implicit-g array (3D, tau_g = 1, FP32 / FP64), else moments_blocks
+long long moments_batch_blocks(const KParams &kp, int prec, bool implicit);
 long long ghost_blocks(const KParams &kp);  // 0 when the step has no ghost launch
 long long collide_blocks(const KParams &kp);  // 0 unless the step is two-kernel
 // first: the first step since the descriptors were written (a simulation's

@@ -654,42 +654,48 @@ __device__ __forceinline__ void implicit_g(Get get, bool low, bool high, Sink si
 // Moments pass of the implicit-g step: rho = sum of the stored f, phi = sum
 // of the delivered g (rebuilt as above), both in population order: the same
 // values and sums as the stored-g pass.  A block is a TX x TY tile of one
-// fluid plane; the five values of the tile, its one-node ring and the
-// planes above and below go through LDS once (each is read by 27 nodes).
+// fluid plane (tile b of the simulation); the five values of the tile, its
+// one-node ring and the planes above and below go through LDS once (each is
+// read by 27 nodes).  imp false: g is stored (the first step after an
+// initialisation or an export), phi = sum of the stored g.
+constexpr int kImpTX = 64, kImpTY = 4;
 template <int PREC, int TX, int TY>
-__global__ void __launch_bounds__(TX * TY)
-k_moments_imp(KParams kp, const typename Ty<PREC>::S *__restrict__ f, const typename Ty<PREC>::R *__restrict__ gp,
-              typename Ty<PREC>::R *__restrict__ rho, typename Ty<PREC>::R *__restrict__ phi)
+__device__ __forceinline__ void moments_imp_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ f,
+                                                 const typename Ty<PREC>::S *__restrict__ g,
+                                                 const typename Ty<PREC>::R *__restrict__ gp,
+                                                 typename Ty<PREC>::R *__restrict__ rho,
+                                                 typename Ty<PREC>::R *__restrict__ phi, unsigned b, bool imp,
+                                                 typename Ty<PREC>::R (*s_p)[3 * (TY + 2) * (TX + 2)])
 {
     using R = typename Ty<PREC>::R;
     using S = typename Ty<PREC>::S;
     constexpr int Q = 27, EX = TX + 2, EY = TY + 2, CELLS = 3 * EY * EX;
     constexpr unsigned SR = sizeof(R);
-    __shared__ R s_p[5][CELLS];
     const int nx = kp.nx, ny = kp.ny, nw = kp.nw;
     const bool walls = kp.walls != 0;
     const unsigned N = (unsigned)kp.N, PS = (unsigned)kp.PS;
     const int ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY;
-    const unsigned b = xcd_block(blockIdx.x, gridDim.x);
     const int tx = (int)(b % (unsigned)ntx), ty = (int)((b / (unsigned)ntx) % (unsigned)nty);
     const int p = (int)(b / (unsigned)(ntx * nty)) + (walls ? 1 : 0);
     const int x0 = tx * TX, y0 = ty * TY;
-    for (int c = threadIdx.x; c < CELLS; c += TX * TY) {
-        const int lx = c % EX, ly = (c / EX) % EY, lz = c / (EX * EY);
-        // periodic wrap without a division (a tile may pass the end of a
-        // small grid more than once)
-        int gx = x0 + lx - 1, gy = y0 + ly - 1;
-        if (gx < 0) gx += nx;
-        while (gx >= nx) gx -= nx;
-        if (gy < 0) gy += ny;
-        while (gy >= ny) gy -= ny;
-        int gz = p + lz - 1;
-        if (!walls) gz = gz < 0 ? gz + nw : (gz >= nw ? gz - nw : gz);
-        const unsigned off = ((unsigned)gz * PS + (unsigned)gy * (unsigned)nx + (unsigned)gx) * SR;
+    if (imp) {
+        for (int c = threadIdx.x; c < CELLS; c += TX * TY) {
+            const int lx = c % EX, ly = (c / EX) % EY, lz = c / (EX * EY);
+            // periodic wrap without a division (a tile may pass the end of a
+            // small grid more than once)
+            int gx = x0 + lx - 1, gy = y0 + ly - 1;
+            if (gx < 0) gx += nx;
+            while (gx >= nx) gx -= nx;
+            if (gy < 0) gy += ny;
+            while (gy >= ny) gy -= ny;
+            int gz = p + lz - 1;
+            if (!walls) gz = gz < 0 ? gz + nw : (gz >= nw ? gz - nw : gz);
+            const unsigned off = ((unsigned)gz * PS + (unsigned)gy * (unsigned)nx + (unsigned)gx) * SR;
 #pragma unroll
-        for (int k = 0; k < 5; ++k) s_p[k][c] = ld32<R>(arr(gp + (size_t)k * N, N), off);
+            for (int k = 0; k < 5; ++k) s_p[k][c] = ld32<R>(arr(gp + (size_t)k * N, N), off);
+        }
+        __syncthreads();
     }
-    __syncthreads();
     const int lx = (int)threadIdx.x % TX, ly = (int)threadIdx.x / TX;
     const int x = x0 + lx, y = y0 + ly;
     if (x >= nx || y >= ny) return;
@@ -700,11 +706,32 @@ k_moments_imp(KParams kp, const typename Ty<PREC>::S *__restrict__ f, const type
     R r = 0, ph = 0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) r += (R)fr[i];
-    const int l0 = (EY + ly + 1) * EX + lx + 1;  // the node in the middle plane
-    auto get = [&](int cx, int cy, int cz, int k) { return s_p[k][l0 - cz * (EX * EY) - cy * EX - cx]; };
-    implicit_g<R>(get, walls && p == 1, walls && p == nw - 2, [&](int, R g) { ph += g; });
+    if (imp) {
+        const int l0 = (EY + ly + 1) * EX + lx + 1;  // the node in the middle plane
+        auto get = [&](int cx, int cy, int cz, int k) { return s_p[k][l0 - cz * (EX * EY) - cy * EX - cx]; };
+        implicit_g<R>(get, walls && p == 1, walls && p == nw - 2, [&](int, R gv) { ph += gv; });
+    } else {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) ph += (R)ld32<S>(arr(g + (size_t)i * N, N), n * (unsigned)sizeof(S));
+    }
     st32<R>(arr(rho, N), n * SR, r);
     st32<R>(arr(phi, N), n * SR, ph);
+}
+
+template <int PREC, int TX, int TY>
+__global__ void __launch_bounds__(TX * TY)
+k_moments_imp(KParams kp, const typename Ty<PREC>::S *__restrict__ f, const typename Ty<PREC>::R *__restrict__ gp,
+              typename Ty<PREC>::R *__restrict__ rho, typename Ty<PREC>::R *__restrict__ phi)
+{
+    __shared__ typename Ty<PREC>::R s_p[5][3 * (TY + 2) * (TX + 2)];
+    moments_imp_tile<PREC, TX, TY>(kp, f, nullptr, gp, rho, phi, xcd_block(blockIdx.x, gridDim.x), true, s_p);
+}
+
+// blocks of the tiled moments pass of one simulation
+inline long long imp_tiles(const KParams &kp)
+{
+    const long long planes = kp.walls ? kp.nw - 2 : kp.nw;
+    return (long long)((kp.nx + kImpTX - 1) / kImpTX) * ((kp.ny + kImpTY - 1) / kImpTY) * planes;
 }
 
 // implicit_g at fluid node n with the values gathered from global memory
@@ -762,17 +789,14 @@ k_moments_batch(const SimDesc *__restrict__ d, const int *__restrict__ sim, int 
     const int pc = sd.pc ^ phase, fc = sd.fc ^ phase;
     const long long t = (long long)(blockIdx.x - sd.mblk0) * blockDim.x + threadIdx.x;
     if constexpr (D == 3 && PREC != P16) {
-        if (sd.gp && (!first || sd.gimp0)) {
-            const long long count = kp.walls ? kp.N - 2 * kp.PS : kp.N;
-            if (t >= count) return;
-            const unsigned n = (unsigned)((kp.walls ? kp.PS : 0) + t), N = (unsigned)kp.N;
-            const S *f = on_global<const S>(d, sd.f[pc]);
-            R r = 0, ph = 0;
-#pragma unroll
-            for (int i = 0; i < 27; ++i) r += (R)ld32<S>(arr(f + (size_t)i * N, N), n * (unsigned)sizeof(S));
-            implicit_g_global<PREC>(kp, on_global<const R>(d, sd.gp), n, [&](int, R g) { ph += g; });
-            st32<R>(arr(on_global<R>(d, sd.rho[1 - fc]), N), n * (unsigned)sizeof(R), r);
-            st32<R>(arr(on_global<R>(d, sd.phi[1 - fc]), N), n * (unsigned)sizeof(R), ph);
+        // simulations with an implicit-g array take the tiled pass (its
+        // block count, imp_tiles), their g implicit or still stored
+        __shared__ R s_p[5][3 * (kImpTY + 2) * (kImpTX + 2)];
+        if (sd.gp) {
+            moments_imp_tile<PREC, kImpTX, kImpTY>(kp, on_global<const S>(d, sd.f[pc]), on_global<const S>(d, sd.g[pc]),
+                                                   on_global<const R>(d, sd.gp), on_global<R>(d, sd.rho[1 - fc]),
+                                                   on_global<R>(d, sd.phi[1 - fc]), blockIdx.x - sd.mblk0,
+                                                   !first || sd.gimp0, s_p);
             return;
         }
     }
@@ -2328,9 +2352,8 @@ int launch_moments_imp(const KParams &kp, int prec, const Buffers &b, int pc, in
 {
     hipStream_t st = (hipStream_t)stream;
     if (kp.D != 3 || !b.gp || prec == P16) return -1;
-    constexpr int TX = 64, TY = 4;
-    const long long planes = kp.walls ? kp.nw - 2 : kp.nw;
-    const long long nb = (long long)((kp.nx + TX - 1) / TX) * ((kp.ny + TY - 1) / TY) * planes;
+    constexpr int TX = kImpTX, TY = kImpTY;
+    const long long nb = imp_tiles(kp);
     if (prec == P64)
         stage_launch(k_moments_imp<P64, TX, TY>, dim3((unsigned)nb), dim3(TX * TY), st, true, true, kp,
                      (SP<P64>)b.f[pc], (RP<P64>)b.gp, (RP<P64>)b.rho[1 - fc], (RP<P64>)b.phi[1 - fc]);
@@ -2509,6 +2532,11 @@ long long collide_blocks(const KParams &kp)
 }
 
 // ------------------------------------------------------- batched launches
+long long moments_batch_blocks(const KParams &kp, int prec, bool implicit)
+{
+    return kp.D == 3 && prec != P16 && implicit ? imp_tiles(kp) : moments_blocks(kp, prec);
+}
+
 long long moments_blocks(const KParams &kp, int prec)
 {
     const long long count = kp.walls ? kp.N - 2 * kp.PS : kp.N;

@@ -5,10 +5,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <condition_variable>
 #include <cstring>
 #include <deque>
 #include <map>
+#include <memory>
+#include <mutex>
 #include <new>
 #include <thread>
 #include <vector>
@@ -61,8 +65,63 @@ struct Arena {
     }
 };
 
+// Calibration of a request's (lambda, kappa) from its tensions and width
+// (lbm3_resolve, host only) runs on worker threads while the GPU steps the
+// resident simulations; a request is admitted once its calibration is done.
+struct Calib {
+    std::atomic<int> state{0};  // 0 pending, 1 done
+    lbm3_params p{};
+    lbm3_status st = LBM3_OK;
+    lbm3_derived d{};
+};
+
+struct CalibPool {
+    std::vector<std::thread> workers;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<std::shared_ptr<Calib>> jobs;
+    bool stop = false;
+    void start(int n)
+    {
+        for (int i = 0; i < n; ++i)
+            workers.emplace_back([this] {
+                for (;;) {
+                    std::shared_ptr<Calib> c;
+                    {
+                        std::unique_lock<std::mutex> lk(mu);
+                        cv.wait(lk, [this] { return stop || !jobs.empty(); });
+                        if (stop && jobs.empty()) return;
+                        c = jobs.front();
+                        jobs.pop_front();
+                    }
+                    c->st = lbm3_resolve(&c->p, &c->d);
+                    c->state.store(1, std::memory_order_release);
+                }
+            });
+    }
+    void push(std::shared_ptr<Calib> c)
+    {
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            jobs.push_back(std::move(c));
+        }
+        cv.notify_one();
+    }
+    void finish()
+    {
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            stop = true;
+        }
+        cv.notify_all();
+        for (auto &t : workers) t.join();
+        workers.clear();
+    }
+};
+
 struct Request {
     uint64_t tag = 0;
+    std::shared_ptr<Calib> calib;  // null once applied to p
     lbm3_params p{};
     std::vector<double> rho0, phi0;
     int64_t nsteps = 0;
@@ -136,6 +195,7 @@ struct lbm3_server {
     size_t sim_bytes = 0;
     Lane lane[kLanes];
     std::deque<Request> queue;
+    CalibPool calib;
     std::deque<lbm3_result> done;
     std::map<uint64_t, Kept> kept;
     std::chrono::steady_clock::time_point t0;
@@ -214,6 +274,24 @@ void admit(lbm3_server *s, int li)
         if (lane_of(r.p) != li) {
             ++it;
             continue;
+        }
+        if (r.calib) {
+            // still calibrating: later requests may go first (not counted as a skip)
+            if (r.calib->state.load(std::memory_order_acquire) == 0) {
+                ++it;
+                continue;
+            }
+            if (r.calib->st != LBM3_OK) {
+                fail_result(s, r, r.calib->st);
+                it = s->queue.erase(it);
+                continue;
+            }
+            r.p.native = 1;
+            for (int k = 0; k < 3; ++k) {
+                r.p.lambda[k] = r.calib->d.lambda[k];
+                r.p.kappa[k] = r.calib->d.kappa[k];
+            }
+            r.calib.reset();
         }
         size_t off = 0;
         int64_t lane_nodes = 0;
@@ -332,6 +410,7 @@ lbm3_status lbm3_server_create(void *pool, size_t pool_bytes, void *stream, int3
         delete s;
         return LBM3_EDEVICE;
     }
+    s->calib.start((int)std::max(1u, std::min(8u, std::thread::hardware_concurrency())));
     s->t0 = std::chrono::steady_clock::now();
     *out = s;
     return LBM3_OK;
@@ -347,19 +426,14 @@ lbm3_status lbm3_server_submit(lbm3_server *s, const lbm3_params *p, const doubl
     r.nsteps = nsteps;
     r.flags = flags;
     r.t_submit = s->now();
-    lbm3_derived d;
-    lbm3_status st = lbm3_resolve(p, &d);
-    if (st != LBM3_OK) {
-        fail_result(s, r, st);
+    // the footprint does not depend on lambda, kappa: checked here, the
+    // calibration itself runs on a worker thread (applied at admission)
+    const size_t fp = lbm3_footprint(&r.p);
+    if (!fp) {
+        fail_result(s, r, LBM3_EINVAL);
         return LBM3_OK;
     }
-    // calibrated here once; the device handle gets lambda, kappa directly
-    r.p.native = 1;
-    for (int k = 0; k < 3; ++k) {
-        r.p.lambda[k] = d.lambda[k];
-        r.p.kappa[k] = d.kappa[k];
-    }
-    r.bytes = align256(lbm3_footprint(&r.p));
+    r.bytes = align256(fp);
     r.table = table_share(r.p);
     if (r.bytes > s->sim_bytes || r.table + kTableSlack > s->lane[lane_of(r.p)].image_cap) {
         fail_result(s, r, LBM3_ENOMEM);
@@ -368,6 +442,11 @@ lbm3_status lbm3_server_submit(lbm3_server *s, const lbm3_params *p, const doubl
     size_t n = (size_t)nodes_of(r.p);
     r.rho0.assign(rho0, rho0 + n);
     r.phi0.assign(phi0, phi0 + n);
+    if (!r.p.native) {
+        r.calib = std::make_shared<Calib>();
+        r.calib->p = r.p;
+        s->calib.push(r.calib);
+    }
     s->queue.push_back(std::move(r));
     return LBM3_OK;
 }
@@ -394,6 +473,13 @@ lbm3_status lbm3_server_run(lbm3_server *s, int64_t quantum, int32_t *n_resident
             if ((st = enqueue_round(l, quantum)) != LBM3_OK) return st;
             acted = acted || l.inflight || s->done.size() != results;
         }
+        // nothing to do yet but a queued request is still calibrating: wait for it
+        if (!acted && !busy)
+            for (const Request &r : s->queue)
+                if (r.calib && r.calib->state.load(std::memory_order_acquire) == 0) {
+                    busy = true;
+                    break;
+                }
         if (acted || !busy) break;
         std::this_thread::sleep_for(std::chrono::microseconds(20));
     }
@@ -434,6 +520,7 @@ lbm3_status lbm3_server_destroy(lbm3_server *s)
         if (q != LBM3_OK) st = q;
         for (auto &r : l.res) lbm3_destroy(r.h);
     }
+    s->calib.finish();
     release_lanes(s);
     delete s;
     return st;

@@ -110,7 +110,7 @@ def test_server_results_equal_runs_alone_and_fit_the_pool():
             break
     for r in srv.poll():
         results[r["tag"]] = r
-    assert results[99]["status"] == -6  # LBM3_ECALIB, reported at submission
+    assert results[99]["status"] == -6  # LBM3_ECALIB, from the calibration on a worker thread
     fields = {}
     for k in range(len(cases)):
         r = results[k]
