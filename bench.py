@@ -335,6 +335,9 @@ def main():
     ap.add_argument("--no-other", action="store_true", help="skip the D2Q9 channel workloads")
     ap.add_argument("--precision", default="fp32", choices=("fp32", "fp16s", "fp64"),
                     help="storage of the timed run (the headline is fp32)")
+    ap.add_argument("--serve-profile", action="store_true",
+                    help="only run the serving burst (batched, then plain) and print the phase clocks; for a "
+                         "kernel trace of the two")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 256 MiB device copy (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -349,6 +352,17 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.serve_profile:
+        reqs = serving_requests(L, I)
+        torch.cuda.synchronize()
+        t0 = time.monotonic_ns()
+        _, span_b, ok_b = run_serving(L, reqs)
+        t1 = time.monotonic_ns()
+        _, span_p, ok_p = run_plain(L, reqs)
+        t2 = time.monotonic_ns()
+        print(json.dumps({"serve_profile": True, "monotonic_ns": [t0, t1, t2], "makespan_batched_s": span_b,
+                          "makespan_plain_s": span_p, "ok": [ok_b, ok_p]}), flush=True)
+        return
     if args.copy_calib:
         x = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
         y = torch.empty_like(x)

@@ -122,7 +122,12 @@ Layout layout(const lbm3_params *p)
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
     for (int k = 0; k < 2; ++k) L.f[k] = take((size_t)Q * N * s);
-    for (int k = 0; k < 2; ++k) L.g[k] = take((size_t)Q * N * s);
+    // implicit g: nothing writes a second g set (the collision stores the
+    // five g^eq values; g is written only by the initialisation and by
+    // exports, each into the current set), so both parities share one
+    if (implicit_g(p)) L.g[0] = L.g[1] = take((size_t)Q * N * s);
+    else
+        for (int k = 0; k < 2; ++k) L.g[k] = take((size_t)Q * N * s);
     for (int k = 0; k < 2; ++k) L.rho[k] = take((size_t)N * r);
     for (int k = 0; k < 2; ++k) L.phi[k] = take((size_t)N * r);
     L.fmu = D == 3 ? take((size_t)(D + 1) * N * r) : 0;  // F, mu_phi of the two-kernel step
