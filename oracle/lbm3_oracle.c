@@ -772,7 +772,38 @@ static void pass_force(or_state *s)
         int k = (ax == 1) ? y : z;
         int first = p->walls && (k == 1 || k == nw - 2);
         double F[3] = {0, 0, 0};
-        if (first) {
+        if (first && p->wall_par == 1) {
+            /* reading (the alternative of Sec. IV and Fig. 4b, a stencil for the
+             * tangential derivatives of P that excludes solid nodes): the
+             * bulk stencil of the tangential terms with every link that
+             * points into the wall replaced by its mirror image on the fluid
+             * side; the wall-normal derivative of P dropped and the
+             * wall-normal ideal link kept, as in the default reading */
+            const int into = (k == 1) ? -1 : 1;
+            double r0 = s->rho[n];
+            for (int i = 0; i < s->Q; ++i) {
+                int c[3] = {s->c[i][0], s->c[i][1], s->c[i][2]};
+                if (c[ax] == into) c[ax] = -into;
+                int xn, yn, zn;
+                neighbour(s, x, y, z, c, &xn, &yn, &zn);
+                int64_t m = idx(s, xn, yn, zn);
+                double pl = link_pressure(r0, s->rho[m]);
+                for (int b = 0; b < p->D; ++b) {
+                    if (b == ax) continue;
+                    for (int a = 0; a < p->D; ++a)
+                        F[a] += 3.0 * s->w[i] * s->c[i][b] * s->Tt[a][b][m];
+                    F[b] += 6.0 * s->w[i] * s->c[i][b] * pl;
+                }
+            }
+            int cp[3] = {0, 0, 0}, cm[3] = {0, 0, 0};
+            cp[ax] = 1;
+            cm[ax] = -1;
+            int xp, yp, zp, xm, ym, zm;
+            neighbour(s, x, y, z, cp, &xp, &yp, &zp);
+            neighbour(s, x, y, z, cm, &xm, &ym, &zm);
+            F[ax] += link_pressure(s->rho[n], s->rho[idx(s, xp, yp, zp)]) -
+                     link_pressure(s->rho[n], s->rho[idx(s, xm, ym, zm)]);
+        } else if (first) {
             for (int b = 0; b < p->D; ++b) {
                 if (b == ax) continue;
                 int cp[3] = {0, 0, 0}, cm[3] = {0, 0, 0};

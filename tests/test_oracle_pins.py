@@ -613,20 +613,58 @@ def test_laplace_law_liquid_liquid():
         assert abs(v - closed) < 0.05 * closed
 
 
-@pytest.mark.parametrize("theta", [60.0, 120.0])
-def test_geometric_wetting_sets_liquid_gas_angle(theta):
-    """Geometric interpolation (Sec. IV B, Eq. 47) imposes the contact angle:
-    a liquid drop in gas started as a 90-degree cap on a 120 x 60 channel
-    ends within 5 degrees of theta_21 after 3000 steps (measured 61.4 and
-    123.8; the paper reports angles within 1 degree on larger drops).  This
-    pins the first-layer wall rule of the force: with the wall-normal link of
-    the ideal part dropped as well, the ghost values stayed out of the contact
-    line's momentum balance and the drops ended near 87 and 94 degrees."""
+def lg_sessile_angle(theta, steps=3000, wall_par=0):
     nx, ny, R = 120, 60, 20.0
-    po = O.make_params(2, (nx, ny), theta_deg=theta)
+    po = O.make_params(2, (nx, ny), theta_deg=theta, wall_par=wall_par)
     sim = O.Sim(po)
     sim.init(*I.cap_drop_2d(nx, ny, R, 90.0))
-    sim.step(3000)
+    sim.step(steps)
     rho, phi = sim.fields()
     C2 = O.concentrations(po, rho, phi)[1]
-    assert abs(O.contact_angle_2d(C2, exclude=8.0)[0] - theta) < 5.0
+    return O.contact_angle_2d(C2, exclude=8.0)[0]
+
+
+@pytest.mark.parametrize("theta,measured", [(60.0, 61.398), (120.0, 123.774)])
+def test_geometric_wetting_sets_liquid_gas_angle(theta, measured):
+    """Geometric interpolation (Sec. IV B, Eq. 47) imposes the contact angle:
+    a liquid drop in gas started as a 90-degree cap on a 120 x 60 channel
+    moves to theta_21 (61.4 and 123.8 degrees after 3000 steps; the band of
+    0.5 degrees around them is a regression bound).  This pins the
+    first-layer wall rule of the force: with the wall-normal link of the
+    ideal part dropped as well, the ghost values stayed out of the contact
+    line's momentum balance and the drops ended near 87 and 94 degrees."""
+    a = lg_sessile_angle(theta)
+    assert abs(a - measured) < 0.5, a
+    assert abs(a - 90.0) > 25.0
+
+
+@pytest.mark.xfail(reason="liquid-gas drops end 1.4 and 3.8 degrees beyond theta_21 on this channel "
+                          "(the excess liquid-gas tension of the link-pressure ideal force)", strict=False)
+@pytest.mark.parametrize("theta", [60.0, 120.0])
+def test_liquid_gas_angle_within_one_degree(theta):
+    """The paper's accuracy claim for the geometric schemes (Sec. IV B)."""
+    assert abs(lg_sessile_angle(theta) - theta) < 1.0
+
+
+def test_wall_stencil_readings_agree_on_wall_parallel_layers():
+    """The two readings of the first-layer tangential derivatives of the
+    force (Sec. IV, Fig. 4b: in-layer central differences, or the bulk
+    stencil with the links into the wall mirrored) differ only through
+    variations along the wall: on a liquid-2 film over liquid 3, layered
+    parallel to the walls, both give the same state (to the rounding of the
+    stencil sums, which cancel exactly only in the central difference); a
+    drop, which varies along the wall, tells them apart."""
+    nx, ny = 24, 30
+    y = np.arange(ny, dtype=float)[:, None] * np.ones((1, nx))
+    C2 = I.profile(10.0 - y, 4.0)
+    out = []
+    for wp in (0, 1):
+        po = O.make_params(2, (nx, ny), theta_deg=75.0, wall_par=wp)
+        sim = O.Sim(po)
+        sim.init(*I.fields_from_conc(C2, 1.0 - C2))
+        sim.step(50)
+        out.append(sim.fields())
+    assert np.abs(out[0][0] - out[1][0]).max() < 1e-12 and np.abs(out[0][1] - out[1][1]).max() < 1e-12
+    a0 = lg_sessile_angle(60.0, steps=200, wall_par=0)
+    a1 = lg_sessile_angle(60.0, steps=200, wall_par=1)
+    assert abs(a0 - a1) > 0.1
