@@ -718,13 +718,90 @@ __device__ __forceinline__ void moments_imp_tile(const KParams &kp, const typena
     st32<R>(arr(phi, N), n * SR, ph);
 }
 
+// The single-simulation implicit-g moments pass as a march: a block takes a
+// TX x TY tile through `chunk` consecutive fluid planes, keeping the five
+// values of three planes (tile and ring) in an LDS ring, so that each plane
+// is staged once per tile instead of three times.  The same values and sums
+// as moments_imp_tile.
 template <int PREC, int TX, int TY>
 __global__ void __launch_bounds__(TX * TY)
 k_moments_imp(KParams kp, const typename Ty<PREC>::S *__restrict__ f, const typename Ty<PREC>::R *__restrict__ gp,
-              typename Ty<PREC>::R *__restrict__ rho, typename Ty<PREC>::R *__restrict__ phi)
+              typename Ty<PREC>::R *__restrict__ rho, typename Ty<PREC>::R *__restrict__ phi, int chunk)
 {
-    __shared__ typename Ty<PREC>::R s_p[5][3 * (TY + 2) * (TX + 2)];
-    moments_imp_tile<PREC, TX, TY>(kp, f, nullptr, gp, rho, phi, xcd_block(blockIdx.x, gridDim.x), true, s_p);
+    using R = typename Ty<PREC>::R;
+    using S = typename Ty<PREC>::S;
+    constexpr int Q = 27, EX = TX + 2, EY = TY + 2, CELLS = EY * EX;
+    constexpr unsigned SR = sizeof(R);
+    __shared__ R s_p[3][5][CELLS];
+    const int nx = kp.nx, ny = kp.ny, nw = kp.nw;
+    const bool walls = kp.walls != 0;
+    const unsigned N = (unsigned)kp.N, PS = (unsigned)kp.PS;
+    const int ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY, ntiles = ntx * nty;
+    const unsigned b = xcd_block(blockIdx.x, gridDim.x);
+    const int tile = (int)(b % (unsigned)ntiles), ch = (int)(b / (unsigned)ntiles);
+    const int x0 = (tile % ntx) * TX, y0 = (tile / ntx) * TY;
+    const int planes = walls ? nw - 2 : nw;
+    const int q0 = ch * chunk, q1 = q0 + chunk < planes ? q0 + chunk : planes;
+    const int off0 = walls ? 1 : 0;
+    // stage plane pz (any plane, ghost planes included) into ring slot `slot`
+    auto stage = [&](int slot, int pz) {
+        if (!walls) pz = pz < 0 ? pz + nw : (pz >= nw ? pz - nw : pz);
+        for (int c = threadIdx.x; c < CELLS; c += TX * TY) {
+            const int lx = c % EX, ly = c / EX;
+            // periodic wrap without a division (a tile may pass the end of a
+            // small grid more than once)
+            int gx = x0 + lx - 1, gy = y0 + ly - 1;
+            if (gx < 0) gx += nx;
+            while (gx >= nx) gx -= nx;
+            if (gy < 0) gy += ny;
+            while (gy >= ny) gy -= ny;
+            const unsigned off = ((unsigned)pz * PS + (unsigned)gy * (unsigned)nx + (unsigned)gx) * SR;
+#pragma unroll
+            for (int k = 0; k < 5; ++k) s_p[slot][k][c] = ld32<R>(arr(gp + (size_t)k * N, N), off);
+        }
+    };
+    const int lx = (int)threadIdx.x % TX, ly = (int)threadIdx.x / TX;
+    const int x = x0 + lx, y = y0 + ly;
+    const bool in = x < nx && y < ny;
+    const int l0 = (ly + 1) * EX + lx + 1;
+    stage(0, q0 + off0 - 1);
+    stage(1, q0 + off0);
+    for (int q = q0; q < q1; ++q) {
+        const int pz = q + off0;
+        const int sm = (q - q0) % 3, sc = (q - q0 + 1) % 3, sp = (q - q0 + 2) % 3;
+        stage(sp, pz + 1);
+        const unsigned n = (unsigned)pz * PS + (unsigned)y * (unsigned)nx + (unsigned)x;
+        S fr[Q];
+        if (in) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) fr[i] = ld32<S>(arr(f + (size_t)i * N, N), n * (unsigned)sizeof(S));
+        }
+        __syncthreads();
+        if (in) {
+            R r = 0, ph = 0;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) r += (R)fr[i];
+            // the source x - c lies in plane pz - cz: below (sm), this (sc) or above (sp)
+            auto get = [&](int cx, int cy, int cz, int k) {
+                const int sl = cz > 0 ? sm : (cz < 0 ? sp : sc);
+                return s_p[sl][k][l0 - cy * EX - cx];
+            };
+            implicit_g<R>(get, walls && pz == 1, walls && pz == nw - 2, [&](int, R gv) { ph += gv; });
+            st32<R>(arr(rho, N), n * SR, r);
+            st32<R>(arr(phi, N), n * SR, ph);
+        }
+        __syncthreads();
+    }
+}
+
+// planes per block of the marching moments pass: about 4096 blocks
+inline int imp_chunk(const KParams &kp, long long ntiles)
+{
+    const long long planes = kp.walls ? kp.nw - 2 : kp.nw;
+    long long c = (ntiles * planes + 4095) / 4096;
+    if (c < 1) c = 1;
+    if (c > planes) c = planes;
+    return (int)c;
 }
 
 // blocks of the tiled moments pass of one simulation
@@ -2353,13 +2430,16 @@ int launch_moments_imp(const KParams &kp, int prec, const Buffers &b, int pc, in
     hipStream_t st = (hipStream_t)stream;
     if (kp.D != 3 || !b.gp || prec == P16) return -1;
     constexpr int TX = kImpTX, TY = kImpTY;
-    const long long nb = imp_tiles(kp);
+    const long long planes = kp.walls ? kp.nw - 2 : kp.nw;
+    const long long ntiles = (long long)((kp.nx + TX - 1) / TX) * ((kp.ny + TY - 1) / TY);
+    const int chunk = imp_chunk(kp, ntiles);
+    const long long nb = ntiles * ((planes + chunk - 1) / chunk);
     if (prec == P64)
         stage_launch(k_moments_imp<P64, TX, TY>, dim3((unsigned)nb), dim3(TX * TY), st, true, true, kp,
-                     (SP<P64>)b.f[pc], (RP<P64>)b.gp, (RP<P64>)b.rho[1 - fc], (RP<P64>)b.phi[1 - fc]);
+                     (SP<P64>)b.f[pc], (RP<P64>)b.gp, (RP<P64>)b.rho[1 - fc], (RP<P64>)b.phi[1 - fc], chunk);
     else
         stage_launch(k_moments_imp<P32, TX, TY>, dim3((unsigned)nb), dim3(TX * TY), st, true, true, kp,
-                     (SP<P32>)b.f[pc], (RP<P32>)b.gp, (RP<P32>)b.rho[1 - fc], (RP<P32>)b.phi[1 - fc]);
+                     (SP<P32>)b.f[pc], (RP<P32>)b.gp, (RP<P32>)b.rho[1 - fc], (RP<P32>)b.phi[1 - fc], chunk);
     return LBM3_CHECK_LAUNCH();
 }
 
