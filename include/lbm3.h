@@ -51,7 +51,7 @@ typedef enum {
     LBM3_OK = 0,
     LBM3_EINVAL = -1,    /* bad shape or parameter */
     LBM3_ENOMEM = -2,    /* workspace smaller than lbm3_footprint() */
-    LBM3_EUNSTABLE = -3, /* observe found NaN / rho <= 0 */
+    LBM3_EUNSTABLE = -3, /* observe found NaN / rho <= 0, or |u + du| >= 1 */
     LBM3_EDEVICE = -4,   /* HIP runtime error */
     LBM3_ESTATE = -5,    /* e.g. step before init */
     LBM3_ECALIB = -6     /* (gamma, width) -> (lambda, kappa) map failed */
@@ -127,6 +127,8 @@ typedef struct {
     int64_t n_bad;          /* nodes with rho <= 0 or non-finite fields */
     int64_t n_newton, n_shortcut, n_fallback; /* entropic alpha kinds since init */
     int64_t step;
+    int64_t n_fast;         /* collisions since init whose velocity u + du had
+                               |u + du| >= 1 (u the bare velocity, du = F/rho) */
 } lbm3_obs;
 
 enum { LBM3_OBS_SUMS = 1u, LBM3_OBS_FIELDS = 2u, LBM3_OBS_POPS = 4u };
@@ -174,7 +176,8 @@ lbm3_status lbm3_step_profiled(lbm3 *h, int64_t nsteps, int32_t sample_every, do
  * bits.  out may be NULL unless LBM3_OBS_SUMS is set.  rho_out/phi_out
  * (N doubles, full grid, ghost layers as last filled) with LBM3_OBS_FIELDS;
  * f_out/g_out (Q*N doubles, [Q][N]) with LBM3_OBS_POPS.  Returns
- * LBM3_EUNSTABLE when the sums found NaN or rho <= 0. */
+ * LBM3_EUNSTABLE when the sums found NaN or rho <= 0, or a collision since
+ * init had |u + du| >= 1 (n_fast). */
 lbm3_status lbm3_observe(lbm3 *h, uint32_t what, lbm3_obs *out, double *rho_out,
                          double *phi_out, double *f_out, double *g_out);
 

@@ -47,6 +47,7 @@ struct or_state {
     double *alpha;
     int64_t step;
     int64_t n_newton, n_shortcut, n_fallback;
+    int64_t n_fast;           /* collisions with |u + du| >= 1 */
 };
 
 /* ------------------------------------------------------------------------ */
@@ -865,8 +866,8 @@ static void pass_collide(or_state *s)
 {
     const or_params *p = &s->p;
     int Q = s->Q;
-    int64_t nn = 0, ns = 0, nf = 0;
-#pragma omp parallel for schedule(static) reduction(+ : nn, ns, nf)
+    int64_t nn = 0, ns = 0, nf = 0, nq = 0;
+#pragma omp parallel for schedule(static) reduction(+ : nn, ns, nf, nq)
     for (int64_t n = 0; n < s->N; ++n) {
         int x, y, z;
         coords(s, n, &x, &y, &z);
@@ -886,6 +887,8 @@ static void pass_collide(or_state *s)
             ud[a] = u[a] + du;
             v[a] = u[a] + 0.5 * du;
         }
+        /* the velocity the collision uses has reached the lattice speed */
+        if (ud[0] * ud[0] + ud[1] * ud[1] + ud[2] * ud[2] >= 1.0) nq += 1;
         double fe[MAXQ], fed[MAXQ], fp[MAXQ], dl[MAXQ];
         or_feq(p->D, r, u, fe);
         or_feq(p->D, r, ud, fed);
@@ -912,6 +915,7 @@ static void pass_collide(or_state *s)
     }
     s->n_newton += nn;
     s->n_shortcut += ns;
+    s->n_fast += nq;
     s->n_fallback += nf;
 }
 
@@ -970,7 +974,7 @@ int or_init(or_state *s, const double *rho0, const double *phi0)
         }
     }
     s->step = 0;
-    s->n_newton = s->n_shortcut = s->n_fallback = 0;
+    s->n_newton = s->n_shortcut = s->n_fallback = s->n_fast = 0;
     pass_moments(s);
     pass_ghost(s);
     return 0;
@@ -1077,6 +1081,7 @@ void or_observe(const or_state *s, or_obs *o)
     o->n_newton = s->n_newton;
     o->n_shortcut = s->n_shortcut;
     o->n_fallback = s->n_fallback;
+    o->n_fast = s->n_fast;
     o->step = s->step;
 }
 

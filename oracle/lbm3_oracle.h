@@ -64,6 +64,7 @@ typedef struct {
     int64_t n_bad;         /* nodes with rho <= 0 or a non-finite field */
     int64_t n_newton, n_shortcut, n_fallback;  /* alpha statistics since init */
     int64_t step;
+    int64_t n_fast;        /* collisions since init with |u + du| >= 1 (du = F/rho) */
 } or_obs;
 
 /* --- thermodynamics ------------------------------------------------------ */

@@ -42,7 +42,7 @@ class OrObs(C.Structure):
         ("mass", C.c_double * 3), ("rho_sum", C.c_double), ("phi_sum", C.c_double),
         ("mom", C.c_double * 3), ("kinetic", C.c_double), ("umax", C.c_double),
         ("n_bad", C.c_int64), ("n_newton", C.c_int64), ("n_shortcut", C.c_int64),
-        ("n_fallback", C.c_int64), ("step", C.c_int64),
+        ("n_fallback", C.c_int64), ("step", C.c_int64), ("n_fast", C.c_int64),
     ]
 
 
@@ -310,7 +310,7 @@ class Sim:
         return {"mass": list(o.mass), "rho_sum": o.rho_sum, "phi_sum": o.phi_sum,
                 "mom": list(o.mom), "kinetic": o.kinetic, "umax": o.umax,
                 "n_bad": o.n_bad, "n_newton": o.n_newton, "n_shortcut": o.n_shortcut,
-                "n_fallback": o.n_fallback, "step": o.step}
+                "n_fallback": o.n_fallback, "step": o.step, "n_fast": o.n_fast}
 
     def concentrations(self):
         r, ph = self.fields()

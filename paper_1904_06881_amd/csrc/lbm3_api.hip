@@ -494,9 +494,9 @@ lbm3_status lbm3_observe(lbm3 *h, uint32_t what, lbm3_obs *out, double *rho_out,
                                 hipMemcpyDeviceToHost, h->stream)) != hipSuccess)
             return hip_err(h, e, "observe download");
         if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return hip_err(h, e, "observe");
-        unsigned long long c[3] = {0, 0, 0};
+        unsigned long long c[4] = {0, 0, 0, 0};
         for (size_t k = 0; k < nslots; ++k)
-            for (int q = 0; q < 3; ++q) c[q] += slots[k * lbm3k::kCntStride + q];
+            for (int q = 0; q < 4; ++q) c[q] += slots[k * lbm3k::kCntStride + q];
         for (int q = 0; q < 3; ++q) out->mass[q] = r[q];
         out->rho_sum = r[3];
         out->phi_sum = r[4];
@@ -507,8 +507,11 @@ lbm3_status lbm3_observe(lbm3 *h, uint32_t what, lbm3_obs *out, double *rho_out,
         out->n_newton = (int64_t)c[0];
         out->n_shortcut = (int64_t)c[1];
         out->n_fallback = (int64_t)c[2];
+        out->n_fast = (int64_t)c[3];
         out->step = h->step;
         if (out->n_bad > 0) status = set_err(h, LBM3_EUNSTABLE, "NaN or non-positive density in the state");
+        else if (out->n_fast > 0)
+            status = set_err(h, LBM3_EUNSTABLE, "a collision had |u + du| >= 1 (the lattice speed)");
     }
     if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return hip_err(h, e, "observe");
     return status;

@@ -236,6 +236,16 @@ __device__ __forceinline__ void feq(R rho, const R *u, R *fe)
     }
 }
 
+// The velocity the collision uses, u + du, has reached the lattice speed:
+// |u + du| >= 1 (counted as an instability next to NaN and rho <= 0)
+template <int D, typename R> __device__ __forceinline__ bool too_fast(const R *u, const R *du)
+{
+    R s = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) s += (u[a] + du[a]) * (u[a] + du[a]);
+    return s >= (R)1;
+}
+
 // Entropic alpha: non-trivial root of H(f' + alpha Delta) = H(f'), Eqs. 30-32,
 // as G(alpha) = sum f'[(1 + alpha x) log1p(alpha x) - alpha x] - alpha K,
 // x = Delta/f', K = sum f' x log1p(x): the terms linear in ln(f^eq/w) and
@@ -1162,7 +1172,7 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
     constexpr bool QR = !(D == 2 && NTH <= 64);
     __shared__ R s_q[5][QR ? FS : 1];
     __shared__ R s_t[3][NP + 1][TS];
-    __shared__ int s_cnt[3];
+    __shared__ int s_cnt[4];
 
     const int tid = threadIdx.x;
     const int nx = kp.nx, ny = kp.ny, nw = kp.nw;
@@ -1173,7 +1183,7 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
     int pb, pe;
     chunk_range(kp, wall_edge(kp, D == 2 && NTH <= 64, chunk), chunk, by, pb, pe);
     if (pb >= pe) return;
-    if (tid < 3) s_cnt[tid] = 0;
+    if (tid < 4) s_cnt[tid] = 0;
 
     Thermo<R> th;
     th.load(kp);
@@ -1402,14 +1412,16 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
     auto nbi = [&](int i) -> unsigned {
         return D == 3 ? nb[(cdir(D, i, 0) + 1) * 3 + cdir(D, i, 1) + 1] : nb[cdir(D, i, 0) + 1];
     };
-    // alpha kinds of the wave's nodes, counted per plane with ballots
-    unsigned long long wave_cnt[3] = {0, 0, 0};
+    // alpha kinds of the wave's nodes and its nodes with |u + du| >= 1,
+    // counted per plane with ballots
+    unsigned long long wave_cnt[4] = {0, 0, 0, 0};
+    auto wc = [&](int k) { return k == 0 ? wave_cnt[0] : (k == 1 ? wave_cnt[1] : (k == 2 ? wave_cnt[2] : wave_cnt[3])); };
     // small 2D class: the block's own running counts (every lane loads, so
     // the load is not under a branch), stored back at the end
     constexpr bool OWNSLOT = D == 2 && NTH <= 64 && !SPLIT;
     unsigned long long *const bslot = OWNSLOT ? cnt + (size_t)(kCntSlots + by * ntx + bx) * kCntStride : nullptr;
     unsigned long long run_cnt = 0;
-    if constexpr (OWNSLOT) run_cnt = bslot[tid < 3 ? tid : 2];
+    if constexpr (OWNSLOT) run_cnt = bslot[tid < 4 ? tid : 3];
 
     if (ONE) pe = pb + 1;
     for (int p = pb; p < pe; ++p) {
@@ -1423,6 +1435,7 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
         compute_T(p + 1);
         __syncthreads();
         int kind_p = -1;
+        bool fast_p = false;
         if (active) {
             const int sm = (p + 9) % 5, s0 = (p + 10) % 5, sp = (p + 11) % 5;
             const int tm = (p + 9) % 3, t0 = (p + 10) % 3, tp = (p + 11) % 3;
@@ -1500,6 +1513,7 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
                     du[a] = F[a] * ir;
                     v[a] = u[a] + (R)0.5 * du[a];
                 }
+                fast_p = collide && too_fast<D, R>(u, du);
                 if (collide) kind_p = collide_f<D, R>(f, r0, u, du, beta, aeps, atol, kp.alpha_maxit, alpha2);
                 // g populations (Eqs. 33-35 below), loaded ahead of the f stores
                 R gg[Q];
@@ -1547,6 +1561,7 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
             wave_cnt[0] += __popcll(__ballot(kind_p == 1));
             wave_cnt[1] += __popcll(__ballot(kind_p == 0));
             wave_cnt[2] += __popcll(__ballot(kind_p == 2));
+            wave_cnt[3] += __popcll(__ballot(fast_p));
         }
         __syncthreads();
     }
@@ -1555,17 +1570,16 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
     // its counter slot directly; the small 2D class stores its own slot)
     unsigned long long *slot = cnt + (size_t)((bx + by * 7) & (kCntSlots - 1)) * kCntStride;
     if constexpr (OWNSLOT) {
-        if (tid < 3) bslot[tid] = run_cnt + wave_cnt[tid == 0 ? 0 : (tid == 1 ? 1 : 2)];
+        if (tid < 4) bslot[tid] = run_cnt + wc(tid);
     } else if constexpr (NTH <= 64) {
-        if (tid < 3 && wave_cnt[tid == 0 ? 0 : (tid == 1 ? 1 : 2)])
-            atomicAdd(&slot[tid], wave_cnt[tid == 0 ? 0 : (tid == 1 ? 1 : 2)]);
+        if (tid < 4 && wc(tid)) atomicAdd(&slot[tid], wc(tid));
     } else {
         if ((tid & 63) == 0)
 #pragma unroll
-            for (int k = 0; k < 3; ++k)
+            for (int k = 0; k < 4; ++k)
                 if (wave_cnt[k]) atomicAdd(&s_cnt[k], (int)wave_cnt[k]);
         __syncthreads();
-        if (tid < 3 && s_cnt[tid]) atomicAdd(&slot[tid], (unsigned long long)s_cnt[tid]);
+        if (tid < 4 && s_cnt[tid]) atomicAdd(&slot[tid], (unsigned long long)s_cnt[tid]);
     }
 }
 
@@ -1921,7 +1935,7 @@ __device__ __forceinline__ int collide_node(const KParams &kp, const typename Ty
                                             const typename Ty<PREC>::R *__restrict__ phi,
                                             const typename Ty<PREC>::R *__restrict__ rprev,
                                             const typename Ty<PREC>::R *__restrict__ pprev,
-                                            const typename Ty<PREC>::R *__restrict__ fmu, long long t)
+                                            const typename Ty<PREC>::R *__restrict__ fmu, long long t, bool &fast)
 {
     using R = typename Ty<PREC>::R;
     using S = typename Ty<PREC>::S;
@@ -1991,6 +2005,7 @@ __device__ __forceinline__ int collide_node(const KParams &kp, const typename Ty
         v[a] = u[a] + (R)0.5 * du[a];
     }
     int kind = -1;
+    fast = collide && too_fast<D, R>(u, du);
     if (collide) kind = collide_f<D, R>(f, r0, u, du, beta, (R)kp.alpha_eps, (R)kp.alpha_tol, kp.alpha_maxit, alpha2);
     // g loads ahead of the f stores (loads and stores retire in order)
     R gg[Q];
@@ -2039,14 +2054,17 @@ __device__ __forceinline__ int collide_node(const KParams &kp, const typename Ty
     return kind;
 }
 
-// alpha statistics of a block: per wave counted with a ballot, summed in LDS
-__device__ __forceinline__ void count_kinds(int kind, int *s_cnt)
+// alpha statistics of a block and its nodes with |u + du| >= 1: per wave
+// counted with a ballot, summed in LDS
+__device__ __forceinline__ void count_kinds(int kind, bool fast, int *s_cnt)
 {
     const unsigned long long nw_ = __ballot(kind == 1), ns_ = __ballot(kind == 0), nf_ = __ballot(kind == 2);
+    const unsigned long long nq_ = __ballot(fast);
     if ((threadIdx.x & 63) == 0) {
         if (nw_) atomicAdd(&s_cnt[0], __popcll(nw_));
         if (ns_) atomicAdd(&s_cnt[1], __popcll(ns_));
         if (nf_) atomicAdd(&s_cnt[2], __popcll(nf_));
+        if (nq_) atomicAdd(&s_cnt[3], __popcll(nq_));
     }
 }
 
@@ -2062,16 +2080,18 @@ k_collide(KParams kp, const typename Ty<PREC>::S *__restrict__ fin, const typena
           const typename Ty<PREC>::R *__restrict__ rprev, const typename Ty<PREC>::R *__restrict__ pprev,
           const typename Ty<PREC>::R *__restrict__ fmu, unsigned long long *__restrict__ cnt)
 {
-    __shared__ int s_cnt[3];
-    if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0;
+    __shared__ int s_cnt[4];
+    if (threadIdx.x < 4) s_cnt[threadIdx.x] = 0;
     __syncthreads();
     const long long count = kp.walls ? kp.N - 2 * kp.PS : kp.N;
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     int kind = -1;
-    if (t < count) kind = collide_node<D, PREC, UNI, GL>(kp, fin, gin, fout, gout, rho, phi, rprev, pprev, fmu, t);
-    count_kinds(kind, s_cnt);
+    bool fast = false;
+    if (t < count)
+        kind = collide_node<D, PREC, UNI, GL>(kp, fin, gin, fout, gout, rho, phi, rprev, pprev, fmu, t, fast);
+    count_kinds(kind, fast, s_cnt);
     __syncthreads();
-    if (threadIdx.x < 3 && s_cnt[threadIdx.x])
+    if (threadIdx.x < 4 && s_cnt[threadIdx.x])
         atomicAdd(&cnt[(size_t)(blockIdx.x & (kCntSlots - 1)) * kCntStride + threadIdx.x],
                   (unsigned long long)s_cnt[threadIdx.x]);
 }
@@ -2082,8 +2102,8 @@ k_collide_batch(const SimDesc *__restrict__ d, const int *__restrict__ sim, int 
 {
     using R = typename Ty<PREC>::R;
     using S = typename Ty<PREC>::S;
-    __shared__ int s_cnt[3];
-    if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0;
+    __shared__ int s_cnt[4];
+    if (threadIdx.x < 4) s_cnt[threadIdx.x] = 0;
     __syncthreads();
     const SimDesc &sd = d[sim[blockIdx.x]];
     const KParams &kp = sd.kp;
@@ -2091,6 +2111,7 @@ k_collide_batch(const SimDesc *__restrict__ d, const int *__restrict__ sim, int 
     const long long count = kp.walls ? kp.N - 2 * kp.PS : kp.N;
     const long long t = (long long)(blockIdx.x - sd.cblk0) * blockDim.x + threadIdx.x;
     int kind = -1;
+    bool fast = false;
     // the same arithmetic either way; a plane stride that is a multiple of
     // the wave makes the bounce-back branches scalar (block-uniform test)
     // implicit g (gp set: tau_g = 1 with collisions): the five values go to gp
@@ -2099,7 +2120,8 @@ k_collide_batch(const SimDesc *__restrict__ d, const int *__restrict__ sim, int 
         return collide_node<D, PREC, decltype(uni)::value, decltype(gl)::value>(
             kp, on_global<const S>(d, sd.f[pc]), on_global<const S>(d, sd.g[pc]), on_global<S>(d, sd.f[1 - pc]),
             gout, on_global<const R>(d, sd.rho[1 - fc]), on_global<const R>(d, sd.phi[1 - fc]),
-            on_global<const R>(d, sd.rho[fc]), on_global<const R>(d, sd.phi[fc]), on_global<const R>(d, sd.fmu), t);
+            on_global<const R>(d, sd.rho[fc]), on_global<const R>(d, sd.phi[fc]), on_global<const R>(d, sd.fmu), t,
+            fast);
     };
     using G2 = std::integral_constant<int, 2>;
     using G3 = std::integral_constant<int, 3>;
@@ -2114,9 +2136,9 @@ k_collide_batch(const SimDesc *__restrict__ d, const int *__restrict__ sim, int 
         }
         if (!done) kind = uni ? node(std::true_type{}, G2{}) : node(std::false_type{}, G2{});
     }
-    count_kinds(kind, s_cnt);
+    count_kinds(kind, fast, s_cnt);
     __syncthreads();
-    if (threadIdx.x < 3 && s_cnt[threadIdx.x])
+    if (threadIdx.x < 4 && s_cnt[threadIdx.x])
         atomicAdd(&on_global<unsigned long long>(d, sd.counters)[(size_t)(blockIdx.x & (kCntSlots - 1)) * kCntStride +
                                                                threadIdx.x],
                   (unsigned long long)s_cnt[threadIdx.x]);

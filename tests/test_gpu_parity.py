@@ -66,7 +66,7 @@ def test_fp64_2000_steps_cfg1():
     for k in range(3):
         assert abs(og["mass"][k] - oo["mass"][k]) < 1e-9
     # entropic alpha statistics: same kinds, up to rare rounding-level flips
-    for key in ("n_newton", "n_shortcut", "n_fallback"):
+    for key in ("n_newton", "n_shortcut", "n_fallback", "n_fast"):
         assert abs(og[key] - oo[key]) <= max(2, 1e-5 * oo[key]), (key, og[key], oo[key])
 
 
@@ -336,3 +336,32 @@ def test_cfg3_full_size_properties():
         for k in range(3):
             assert abs(o["mass"][k] - o0["mass"][k]) <= tol * max(abs(o0["mass"][k]), 1e-3 * nF)
         del s
+
+
+@pytest.mark.parametrize("D", [2, 3])
+@pytest.mark.parametrize("lam", [2.0, 2.5])
+def test_too_fast_count_matches_oracle(D, lam):
+    """|u + du| >= 1 collisions (the observables' n_fast, and LBM3_EUNSTABLE
+    from observe) counted as the oracle counts them: a sharp flat liquid-gas
+    interface, 1 and 3 steps, FP64; in 3D through the two-kernel step (a
+    quasi-2D slab, 4 planes)."""
+    nx, ny = 32, 16
+    rho0, phi0 = I.flat_interface_2d(nx, ny, left=(0, 0), right=(1, 0), W=2.0)
+    n = (nx, ny) if D == 2 else (nx, ny, 4)
+    if D == 3:
+        rho0, phi0 = np.repeat(rho0[None], 4, axis=0), np.repeat(phi0[None], 4, axis=0)
+    p = L.make_params(L.D2Q9 if D == 2 else L.D3Q27, n, walls=False, rho_l=1.0, rho_g=1e-3,
+                      lam=(lam, lam, lam), kap=(0.03, 0.03, 0.03), precision=L.FP64)
+    s = L.Sim(p)
+    s.init(rho0, phi0)
+    ora = O.Sim(oracle_params_from(p, s.derived))
+    ora.init(rho0, phi0)
+    for k in (1, 2):
+        s.step(k)
+        ora.step(k)
+        g, o = s.observe(), ora.observe()
+        say("too fast", D, lam, "gpu", g["n_fast"], "oracle", o["n_fast"], "status", g["status"])
+        assert g["n_fast"] == o["n_fast"] and g["n_bad"] == o["n_bad"]
+        if g["n_bad"] == 0:
+            assert (g["status"] == -3) == (g["n_fast"] > 0)
+    s.close()

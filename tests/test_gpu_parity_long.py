@@ -160,7 +160,7 @@ def test_observables_match_oracle(D):
     assert abs(og["kinetic"] - oo["kinetic"]) <= 1e-9 * oo["kinetic"]
     assert abs(og["umax"] - oo["umax"]) <= 1e-9 * oo["umax"]
     assert oo["kinetic"] > 0 and oo["umax"] > 0
-    for key in ("n_newton", "n_shortcut", "n_fallback"):
+    for key in ("n_newton", "n_shortcut", "n_fallback", "n_fast"):
         assert abs(og[key] - oo[key]) <= max(2, 1e-5 * oo[key]), key
 
 

@@ -49,7 +49,7 @@ def alone(p, init, nsteps, counts=None):
     out = s.fields() + s.pops()
     if counts is not None:
         o = s.observe()
-        counts.extend(o[k] for k in ("n_newton", "n_shortcut", "n_fallback"))
+        counts.extend(o[k] for k in ("n_newton", "n_shortcut", "n_fallback", "n_fast"))
     s.close()
     return out
 
@@ -79,7 +79,7 @@ def test_batched_steps_equal_steps_alone():
         assert o["step"] == 31
         # the entropic-alpha statistics, counted in the batched kernels'
         # own slots, equal those of the run alone
-        assert [o[q] for q in ("n_newton", "n_shortcut", "n_fallback")] == cref, k
+        assert [o[q] for q in ("n_newton", "n_shortcut", "n_fallback", "n_fast")] == cref, k
         sims[k].close()
 
 

@@ -668,3 +668,22 @@ def test_wall_stencil_readings_agree_on_wall_parallel_layers():
     a0 = lg_sessile_angle(60.0, steps=200, wall_par=0)
     a1 = lg_sessile_angle(60.0, steps=200, wall_par=1)
     assert abs(a0 - a1) > 0.1
+
+
+@pytest.mark.parametrize("lam,fast", [(2.0, False), (2.5, True)])
+def test_too_fast_collisions_are_counted(lam, fast):
+    """The instability count of the observables: collisions whose velocity
+    u + du (du = F/rho) reached the lattice speed.  A sharp flat liquid-gas
+    interface (width 2) of growing equation-of-state weight: at lambda = 2.5
+    the gas nodes beside it are pushed past |u + du| = 1 in the first step
+    while every density stays positive; at lambda = 2 none is."""
+    po = O.make_params(2, (32, 16), walls=False, rho_l=1.0, rho_g=1e-3, lam=(lam, lam, lam),
+                       kap=(0.03, 0.03, 0.03))
+    s = O.Sim(po)
+    s.init(*I.flat_interface_2d(32, 16, left=(0, 0), right=(1, 0), W=2.0))
+    s.step(1)
+    o = s.observe()
+    assert o["n_bad"] == 0
+    assert (o["n_fast"] > 0) == fast
+    if fast:
+        assert o["n_fast"] % 16 == 0  # whole columns of the x-layered state
