@@ -55,19 +55,24 @@ def kernel_bytes(Q, s, sf, fp16, g_read, implicit_g):
       stencil  read rho, phi, write F (3) and mu_phi;
       collide  read f (and g unless tau_g = 1), rho, phi, F, mu_phi (FP16:
                the previous fields), write both population sets.
-    With implicit g (tau_g = 1, FP32 / FP64: the collision stores the five
-    values (a, phi, v) that fix g^eq instead of the 27 g):
-      moments  read f and the five values (each node's once), write rho, phi;
-      collide  read f, rho, phi, F, mu_phi, write f and the five values.
+    With implicit g (tau_g = 1: the collision stores the five values (a, phi,
+    v) that fix g^eq, in the compute type, instead of the 27 g):
+      moments  read f and the five values (each node's once), write rho, phi
+               (FP16 storage: and read the density f was encoded with);
+      collide  read f, rho, phi, F, mu_phi, write f and the five values
+               (FP16: and the density f was encoded with).
     step_alg: the step's algorithmic minimum for stored populations, 4 Q s +
     4 sf (read and write both population sets once, write and read rho, phi
     once); step_path: the same minimum for the path that runs (implicit g:
-    2 Q s + 14 sf, the five values written and read once in place of g)."""
+    2 Q s + 14 sf, the five values written and read once in place of g; FP16
+    storage: + 2 sf for the decoding densities)."""
     dec = 2 * sf if fp16 else 0
     std = 4 * Q * s + 4 * sf
     if implicit_g:
-        return {"moments": Q * s + 5 * sf + 2 * sf, "stencil": 6 * sf,
-                "collide": 2 * Q * s + 6 * sf + 5 * sf, "step_alg": std, "step_path": 2 * Q * s + 14 * sf}
+        d1 = sf if fp16 else 0
+        return {"moments": Q * s + 5 * sf + 2 * sf + d1, "stencil": 6 * sf,
+                "collide": 2 * Q * s + 6 * sf + 5 * sf + d1, "step_alg": std,
+                "step_path": 2 * Q * s + 14 * sf + 2 * d1}
     return {"moments": 2 * Q * s + 2 * sf + dec,
             "stencil": 6 * sf,
             "collide": (2 if g_read else 1) * Q * s + 2 * Q * s + 6 * sf + dec,
@@ -380,7 +385,7 @@ def main():
     ms_step = 1e3 * wall / args.steps
     mlups = fluid * args.steps / wall / 1e6
 
-    kb = kernel_bytes(27, s, sf, fp16, g_read=False, implicit_g=not fp16)
+    kb = kernel_bytes(27, s, sf, fp16, g_read=False, implicit_g=True)
     kern = {"moments": prof["moments"], "stencil": prof["stencil"], "collide": prof["collide"],
             "ghost": prof["ghost"]}
     dom = max(("moments", "stencil", "collide"), key=lambda k: kern[k])
@@ -400,7 +405,7 @@ def main():
             Pv, sv, sfv, f16v = precs[name]
             n = 50 if name == "fp16s" else 20
             w, pr, o = run3(L, I, Pv, n, 5, init=init)
-            kv = kernel_bytes(27, sv, sfv, f16v, g_read=False, implicit_g=not f16v)
+            kv = kernel_bytes(27, sv, sfv, f16v, g_read=False, implicit_g=True)
             mv = fluid * n / w / 1e6
             variants[name] = {"MLUPS": mv, "ms_per_step": 1e3 * w / n, "moments_ms": pr["moments"],
                               "stencil_ms": pr["stencil"], "collide_ms": pr["collide"],

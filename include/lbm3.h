@@ -69,8 +69,10 @@ enum {
     LBM3_STORED_G = 8u      /* D3Q27 with tau_g = 1: store and stream the 27 g
                                populations instead of the default implicit g
                                (the collision keeps (a, phi, v) of g^eq per
-                               node, Eqs. 33-35, and the moments pass rebuilds
-                               the streamed g from them); bit-identical results */
+                               node, Eqs. 33-35, in the compute type, and the
+                               moments pass rebuilds the streamed g from them);
+                               bit-identical results in FP32 and FP64 (with
+                               FP16 storage the implicit g is not rounded) */
 };
 
 /* Problem statement (paper Sec. II-IV).  Zero-initialise, then set. */

@@ -28,6 +28,7 @@ struct lbm3 {
     hipStream_t stream;
     int pc, fc;            // current population buffer, fields it is encoded with
     bool gimp;             // g[pc] not written: the last collision stored (a, phi, v) in b.gp
+    bool gmat;             // with gimp: g[pc] holds the implicit g written out (for readers of g)
     bool inited;
     int64_t step;
     std::string err;
@@ -101,13 +102,14 @@ size_t counter_slots(const lbm3_params *p)
     return (size_t)lbm3k::kCntSlots + (size_t)lbm3k::small2d_block_slots(D, p->n[0], p->n[D - 1]);
 }
 
-// tau_g = 1 with collisions in the 3D two-kernel step (FP32 / FP64): the
-// post-collision g is g^eq of (a, phi, v), Eqs. 33-35, so the collision
-// stores those five values per node (20 or 40 bytes) instead of pushing 27
-// populations, and the next moments pass rebuilds the delivered g from them
+// tau_g = 1 with collisions in the 3D two-kernel step: the post-collision g
+// is g^eq of (a, phi, v), Eqs. 33-35, so the collision stores those five
+// values per node in the compute type (20 bytes, 40 in FP64) instead of
+// pushing 27 populations, and the next moments pass rebuilds the delivered
+// g from them (with FP16 storage g is then never rounded to FP16)
 bool implicit_g(const lbm3_params *p)
 {
-    return p->lattice == LBM3_D3Q27 && p->precision != LBM3_FP16S && p->tau_g == 1.0 &&
+    return p->lattice == LBM3_D3Q27 && p->tau_g == 1.0 &&
            !(p->flags & (LBM3_NO_COLLIDE | LBM3_FUSED_3D | LBM3_STORED_G));
 }
 
@@ -264,7 +266,7 @@ lbm3_status lbm3_create(const lbm3_params *p, void *ws, size_t bytes, void *stre
     b.result = (double *)(base + L.result);
     b.n_partials = 1024;
     h->pc = h->fc = 0;
-    h->gimp = false;
+    h->gimp = h->gmat = false;
     h->inited = false;
     h->step = 0;
     *out = h;
@@ -304,6 +306,7 @@ lbm3_status lbm3_init(lbm3 *h, const double *rho0, const double *phi0)
         return hip_err(h, e, "counters");
     if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return hip_err(h, e, "init");
     h->pc = h->fc = 0;
+    h->gimp = h->gmat = false;  // the populations just written are stored, g included
     h->step = 0;
     h->inited = true;
     return LBM3_OK;
@@ -317,12 +320,14 @@ static int launch_moments(lbm3 *h)
                    : lbm3k::launch_moments(h->kp, h->prec, h->b, h->pc, h->fc, h->stream);
 }
 
-// g[pc] written out where something reads the stored g
+// g[pc] written out where something reads the stored g.  The state stays
+// implicit: the next moments pass still rebuilds g from the five values
+// (with FP16 storage the written copy is rounded, the five values are not).
 static int materialize_g(lbm3 *h, hipStream_t st)
 {
-    if (!h->gimp) return 0;
-    if (lbm3k::launch_g_materialize(h->kp, h->prec, h->b, h->pc, st)) return -1;
-    h->gimp = false;
+    if (!h->gimp || h->gmat) return 0;
+    if (lbm3k::launch_g_materialize(h->kp, h->prec, h->b, h->pc, h->fc, st)) return -1;
+    h->gmat = true;
     return 0;
 }
 
@@ -333,6 +338,7 @@ static void stepped(lbm3 *h)
     h->fc ^= 1;
     h->step++;
     h->gimp = h->b.gp != nullptr;
+    h->gmat = false;
 }
 
 static int launch_step(lbm3 *h, int which)
@@ -812,7 +818,10 @@ lbm3_status enqueue(lbm3 *const *hs, int m, const Image &img, const void *dev_ba
             hs[i]->fc ^= 1;
         }
         hs[i]->step += steps;
-        if (steps > 0 && hs[i]->b.gp) hs[i]->gimp = true;
+        if (steps > 0 && hs[i]->b.gp) {
+            hs[i]->gimp = true;
+            hs[i]->gmat = false;
+        }
     }
     return LBM3_OK;
 }

@@ -52,7 +52,8 @@ struct Buffers {
     void *f[2], *g[2];           // populations [Q][N], storage type by precision
     void *rho[2], *phi[2];       // fields [N], compute type
     void *fmu;                   // 3D two-kernel step: F, mu_phi [D + 1][N], compute type
-    void *gp;                    // implicit-g step: (a, phi, v) of g^eq [5][N], compute type, or null
+    void *gp;                    // implicit-g step: (a, phi, v) of g^eq [5][N], compute type (FP32 with
+                                 // FP16 storage), or null
     double *scratch;             // N doubles (upload / export staging)
     unsigned long long *counters;// kCntSlots (+ per-block) slots of kCntStride: newton, shortcut, fallback
     double *partials;            // reduction partials
@@ -87,7 +88,7 @@ int launch_moments(const KParams &kp, int prec, const Buffers &b, int pc, int fc
 // implicit-g step (b.gp set): the moments pass that rebuilds g from b.gp, and
 // the kernel that writes that g out into b.g[pc]
 int launch_moments_imp(const KParams &kp, int prec, const Buffers &b, int pc, int fc, void *stream);
-int launch_g_materialize(const KParams &kp, int prec, const Buffers &b, int pc, void *stream);
+int launch_g_materialize(const KParams &kp, int prec, const Buffers &b, int pc, int fc, void *stream);
 int launch_ghost(const KParams &kp, int prec, const Buffers &b, int fdst, void *stream);
 int launch_fused(const KParams &kp, int prec, const Buffers &b, int pc, int fc, void *stream);
 // events (hipEvent_t, or null) the next launch_moments / launch_ghost /
@@ -117,7 +118,7 @@ int observe_blocks(const KParams &kp);
 FusedGeom fused_geometry(const KParams &kp, int prec);
 long long moments_blocks(const KParams &kp, int prec);
 // the batched moments launch: the tiled pass for a simulation with an
-// implicit-g array (3D, tau_g = 1, FP32 / FP64), else moments_blocks
+// implicit-g array (3D, tau_g = 1), else moments_blocks
 long long moments_batch_blocks(const KParams &kp, int prec, bool implicit);
 long long ghost_blocks(const KParams &kp);  // 0 when the step has no ghost launch
 long long collide_blocks(const KParams &kp);  // 0 unless the step is two-kernel

@@ -673,6 +673,8 @@ template <int PREC, int TX, int TY>
 __device__ __forceinline__ void moments_imp_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ f,
                                                  const typename Ty<PREC>::S *__restrict__ g,
                                                  const typename Ty<PREC>::R *__restrict__ gp,
+                                                 const typename Ty<PREC>::R *__restrict__ rprev,
+                                                 const typename Ty<PREC>::R *__restrict__ pprev,
                                                  typename Ty<PREC>::R *__restrict__ rho,
                                                  typename Ty<PREC>::R *__restrict__ phi, unsigned b, bool imp,
                                                  typename Ty<PREC>::R (*s_p)[3 * (TY + 2) * (TX + 2)])
@@ -713,16 +715,22 @@ __device__ __forceinline__ void moments_imp_tile(const KParams &kp, const typena
     S fr[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) fr[i] = ld32<S>(arr(f + (size_t)i * N, N), n * (unsigned)sizeof(S));
+    // FP16 storage: offsets decoded with the fields they were encoded with
+    R rp = 0, pp = 0;
+    if constexpr (PREC == P16) {
+        rp = ld32<R>(arr(rprev, N), n * SR);
+        pp = ld32<R>(arr(pprev, N), n * SR);
+    }
     R r = 0, ph = 0;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) r += (R)fr[i];
+    for (int i = 0; i < Q; ++i) r += dec_f<PREC, 3>(fr[i], i, rp);
     if (imp) {
         const int l0 = (EY + ly + 1) * EX + lx + 1;  // the node in the middle plane
         auto get = [&](int cx, int cy, int cz, int k) { return s_p[k][l0 - cz * (EX * EY) - cy * EX - cx]; };
         implicit_g<R>(get, walls && p == 1, walls && p == nw - 2, [&](int, R gv) { ph += gv; });
     } else {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) ph += (R)ld32<S>(arr(g + (size_t)i * N, N), n * (unsigned)sizeof(S));
+        for (int i = 0; i < Q; ++i) ph += dec_g<PREC, 3>(ld32<S>(arr(g + (size_t)i * N, N), n * (unsigned)sizeof(S)), i, pp);
     }
     st32<R>(arr(rho, N), n * SR, r);
     st32<R>(arr(phi, N), n * SR, ph);
@@ -736,7 +744,8 @@ __device__ __forceinline__ void moments_imp_tile(const KParams &kp, const typena
 template <int PREC, int TX, int TY>
 __global__ void __launch_bounds__(TX * TY)
 k_moments_imp(KParams kp, const typename Ty<PREC>::S *__restrict__ f, const typename Ty<PREC>::R *__restrict__ gp,
-              typename Ty<PREC>::R *__restrict__ rho, typename Ty<PREC>::R *__restrict__ phi, int chunk)
+              const typename Ty<PREC>::R *__restrict__ rprev, typename Ty<PREC>::R *__restrict__ rho,
+              typename Ty<PREC>::R *__restrict__ phi, int chunk)
 {
     using R = typename Ty<PREC>::R;
     using S = typename Ty<PREC>::S;
@@ -782,15 +791,18 @@ k_moments_imp(KParams kp, const typename Ty<PREC>::S *__restrict__ f, const type
         stage(sp, pz + 1);
         const unsigned n = (unsigned)pz * PS + (unsigned)y * (unsigned)nx + (unsigned)x;
         S fr[Q];
+        R rp = 0;
         if (in) {
 #pragma unroll
             for (int i = 0; i < Q; ++i) fr[i] = ld32<S>(arr(f + (size_t)i * N, N), n * (unsigned)sizeof(S));
+            // FP16 storage: offsets decoded with the density they were encoded with
+            if constexpr (PREC == P16) rp = ld32<R>(arr(rprev, N), n * SR);
         }
         __syncthreads();
         if (in) {
             R r = 0, ph = 0;
 #pragma unroll
-            for (int i = 0; i < Q; ++i) r += (R)fr[i];
+            for (int i = 0; i < Q; ++i) r += dec_f<PREC, 3>(fr[i], i, rp);
             // the source x - c lies in plane pz - cz: below (sm), this (sc) or above (sp)
             auto get = [&](int cx, int cy, int cz, int k) {
                 const int sl = cz > 0 ? sm : (cz < 0 ? sp : sc);
@@ -846,7 +858,8 @@ __device__ __forceinline__ void implicit_g_global(const KParams &kp, const typen
 // stored g: observables, exports).
 template <int PREC>
 __global__ void __launch_bounds__(256)
-k_g_materialize(KParams kp, const typename Ty<PREC>::R *__restrict__ gp, typename Ty<PREC>::S *__restrict__ g)
+k_g_materialize(KParams kp, const typename Ty<PREC>::R *__restrict__ gp, const typename Ty<PREC>::R *__restrict__ pcur,
+                typename Ty<PREC>::S *__restrict__ g)
 {
     using R = typename Ty<PREC>::R;
     using S = typename Ty<PREC>::S;
@@ -854,8 +867,12 @@ k_g_materialize(KParams kp, const typename Ty<PREC>::R *__restrict__ gp, typenam
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= count) return;
     const unsigned n = (unsigned)((kp.walls ? kp.PS : 0) + t), N = (unsigned)kp.N;
+    // FP16 storage: the rest population as an offset from the field phi the
+    // next reader decodes it with (the current one)
+    R pn = 0;
+    if constexpr (PREC == P16) pn = ld32<R>(arr(pcur, N), n * (unsigned)sizeof(R));
     implicit_g_global<PREC>(kp, gp, n, [&](int i, R v) {
-        st32<S>(arr(g + (size_t)i * N, N), n * (unsigned)sizeof(S), (S)v);
+        st32<S>(arr(g + (size_t)i * N, N), n * (unsigned)sizeof(S), enc_g<PREC, 3>(v, i, pn));
     });
 }
 
@@ -875,13 +892,14 @@ k_moments_batch(const SimDesc *__restrict__ d, const int *__restrict__ sim, int 
     const KParams &kp = sd.kp;
     const int pc = sd.pc ^ phase, fc = sd.fc ^ phase;
     const long long t = (long long)(blockIdx.x - sd.mblk0) * blockDim.x + threadIdx.x;
-    if constexpr (D == 3 && PREC != P16) {
+    if constexpr (D == 3) {
         // simulations with an implicit-g array take the tiled pass (its
         // block count, imp_tiles), their g implicit or still stored
         __shared__ R s_p[5][3 * (kImpTY + 2) * (kImpTX + 2)];
         if (sd.gp) {
             moments_imp_tile<PREC, kImpTX, kImpTY>(kp, on_global<const S>(d, sd.f[pc]), on_global<const S>(d, sd.g[pc]),
-                                                   on_global<const R>(d, sd.gp), on_global<R>(d, sd.rho[1 - fc]),
+                                                   on_global<const R>(d, sd.gp), on_global<const R>(d, sd.rho[fc]),
+                                                   on_global<const R>(d, sd.phi[fc]), on_global<R>(d, sd.rho[1 - fc]),
                                                    on_global<R>(d, sd.phi[1 - fc]), blockIdx.x - sd.mblk0,
                                                    !first || sd.gimp0, s_p);
             return;
@@ -2029,7 +2047,6 @@ __device__ __forceinline__ int collide_node(const KParams &kp, const typename Ty
     if constexpr (GL == 3) {
         // g* = g^eq is a function of (a, phi, v): store those five values at
         // the node instead of pushing 27 populations
-        static_assert(PREC != P16, "implicit g needs the compute type");
         R *gp = (R *)gout;
         const R vals[5] = {geq_a<D, R>(v, p0, mup, Gam), p0, v[0], v[1], v[2]};
 #pragma unroll
@@ -2128,7 +2145,7 @@ k_collide_batch(const SimDesc *__restrict__ d, const int *__restrict__ sim, int 
     if (t < count) {
         const bool uni = kp.PS % 64 == 0;
         bool done = false;
-        if constexpr (D == 3 && PREC != P16) {
+        if constexpr (D == 3) {
             if (sd.gp) {
                 kind = uni ? node(std::true_type{}, G3{}) : node(std::false_type{}, G3{});
                 done = true;
@@ -2447,33 +2464,40 @@ int launch_moments(const KParams &kp, int prec, const Buffers &b, int pc, int fc
     return moments_t<3, P16>(kp, b, pc, fc, st);
 }
 
-int launch_moments_imp(const KParams &kp, int prec, const Buffers &b, int pc, int fc, void *stream)
+template <int PREC>
+static void moments_imp_t(const KParams &kp, const Buffers &b, int pc, int fc, hipStream_t st)
 {
-    hipStream_t st = (hipStream_t)stream;
-    if (kp.D != 3 || !b.gp || prec == P16) return -1;
     constexpr int TX = kImpTX, TY = kImpTY;
     const long long planes = kp.walls ? kp.nw - 2 : kp.nw;
     const long long ntiles = (long long)((kp.nx + TX - 1) / TX) * ((kp.ny + TY - 1) / TY);
     const int chunk = imp_chunk(kp, ntiles);
     const long long nb = ntiles * ((planes + chunk - 1) / chunk);
-    if (prec == P64)
-        stage_launch(k_moments_imp<P64, TX, TY>, dim3((unsigned)nb), dim3(TX * TY), st, true, true, kp,
-                     (SP<P64>)b.f[pc], (RP<P64>)b.gp, (RP<P64>)b.rho[1 - fc], (RP<P64>)b.phi[1 - fc], chunk);
-    else
-        stage_launch(k_moments_imp<P32, TX, TY>, dim3((unsigned)nb), dim3(TX * TY), st, true, true, kp,
-                     (SP<P32>)b.f[pc], (RP<P32>)b.gp, (RP<P32>)b.rho[1 - fc], (RP<P32>)b.phi[1 - fc], chunk);
+    stage_launch(k_moments_imp<PREC, TX, TY>, dim3((unsigned)nb), dim3(TX * TY), st, true, true, kp,
+                 (SP<PREC>)b.f[pc], (RP<PREC>)b.gp, (RP<PREC>)b.rho[fc], (RP<PREC>)b.rho[1 - fc],
+                 (RP<PREC>)b.phi[1 - fc], chunk);
+}
+
+int launch_moments_imp(const KParams &kp, int prec, const Buffers &b, int pc, int fc, void *stream)
+{
+    hipStream_t st = (hipStream_t)stream;
+    if (kp.D != 3 || !b.gp) return -1;
+    if (prec == P64) moments_imp_t<P64>(kp, b, pc, fc, st);
+    else if (prec == P32) moments_imp_t<P32>(kp, b, pc, fc, st);
+    else moments_imp_t<P16>(kp, b, pc, fc, st);
     return LBM3_CHECK_LAUNCH();
 }
 
-int launch_g_materialize(const KParams &kp, int prec, const Buffers &b, int pc, void *stream)
+int launch_g_materialize(const KParams &kp, int prec, const Buffers &b, int pc, int fc, void *stream)
 {
     hipStream_t st = (hipStream_t)stream;
-    if (kp.D != 3 || !b.gp || prec == P16) return -1;
+    if (kp.D != 3 || !b.gp) return -1;
     const long long count = kp.walls ? kp.N - 2 * kp.PS : kp.N;
     if (prec == P64)
-        k_g_materialize<P64><<<nblk(count, 256), 256, 0, st>>>(kp, (RP<P64>)b.gp, (SP<P64>)b.g[pc]);
+        k_g_materialize<P64><<<nblk(count, 256), 256, 0, st>>>(kp, (RP<P64>)b.gp, (RP<P64>)b.phi[fc], (SP<P64>)b.g[pc]);
+    else if (prec == P32)
+        k_g_materialize<P32><<<nblk(count, 256), 256, 0, st>>>(kp, (RP<P32>)b.gp, (RP<P32>)b.phi[fc], (SP<P32>)b.g[pc]);
     else
-        k_g_materialize<P32><<<nblk(count, 256), 256, 0, st>>>(kp, (RP<P32>)b.gp, (SP<P32>)b.g[pc]);
+        k_g_materialize<P16><<<nblk(count, 256), 256, 0, st>>>(kp, (RP<P16>)b.gp, (RP<P16>)b.phi[fc], (SP<P16>)b.g[pc]);
     return LBM3_CHECK_LAUNCH();
 }
 
@@ -2576,19 +2600,17 @@ static int split_t(const KParams &kp, const Buffers &b, int pc, int fc, hipStrea
     const bool uni = kp.PS % 64 == 0;
     const bool gl = (kp.flags & 1u) || kp.inv_tau_g != 1.0;
     // implicit g: the collision stores (a, phi, v) in b.gp instead of g
-    const bool imp = b.gp != nullptr && !gl && PREC != P16;
+    const bool imp = b.gp != nullptr && !gl;
     auto go = [&](auto kern) {
         stage_launch(kern, dim3((unsigned)collide_blocks(kp)), dim3(256), st, false, true, kp, (SP<PREC>)b.f[pc],
                      (SP<PREC>)b.g[pc], (SP<PREC>)b.f[1 - pc], imp ? (SP<PREC>)b.gp : (SP<PREC>)b.g[1 - pc],
                      (RP<PREC>)b.rho[1 - fc], (RP<PREC>)b.phi[1 - fc], (RP<PREC>)b.rho[fc], (RP<PREC>)b.phi[fc],
                      (RP<PREC>)b.fmu, b.counters);
     };
-    if constexpr (PREC != P16) {
-        if (imp) {
-            if (uni) go(k_collide<3, PREC, true, 3>);
-            else go(k_collide<3, PREC, false, 3>);
-            return LBM3_CHECK_LAUNCH();
-        }
+    if (imp) {
+        if (uni) go(k_collide<3, PREC, true, 3>);
+        else go(k_collide<3, PREC, false, 3>);
+        return LBM3_CHECK_LAUNCH();
     }
     if (uni) {
         if (gl) go(k_collide<3, PREC, true, 1>);
@@ -2636,7 +2658,7 @@ long long collide_blocks(const KParams &kp)
 // ------------------------------------------------------- batched launches
 long long moments_batch_blocks(const KParams &kp, int prec, bool implicit)
 {
-    return kp.D == 3 && prec != P16 && implicit ? imp_tiles(kp) : moments_blocks(kp, prec);
+    return kp.D == 3 && implicit ? imp_tiles(kp) : moments_blocks(kp, prec);
 }
 
 long long moments_blocks(const KParams &kp, int prec)

@@ -15,6 +15,7 @@ import sys
 import numpy as np
 import pytest
 
+from _common import conc
 from paper_1904_06881_amd import inputs as I
 from paper_1904_06881_amd import lbm3 as L
 
@@ -127,3 +128,48 @@ def test_implicit_g_angle_and_footprint():
     a = run("walled", L.FP32, 0, [("step", 20), ("angle",)])
     b = run("walled", L.FP32, L.STORED_G, [("step", 20), ("angle",)])
     assert np.array_equal(a[0], b[0]) and np.isfinite(a[0]).all()
+
+
+@pytest.mark.parametrize("kind", ["walled", "periodic"])
+def test_implicit_g_fp16_storage(kind):
+    """FP16 population storage with implicit g: f stored as FP16 offsets, g
+    rebuilt from the five FP32 values (so never rounded to FP16).  Against
+    the stored-g FP16 form and the FP64 run after 60 steps: both FP16 forms
+    within the FP16-storage bound (2e-3 max-abs C_k) of FP64, and the
+    implicit one no farther from it than the stored one plus 1e-4."""
+    p64, init = case(kind, L.FP64)
+    runs = {}
+    for name, prec, flags in (("fp64", L.FP64, 0), ("imp", L.FP16S, 0), ("stored", L.FP16S, L.STORED_G)):
+        p, _ = case(kind, prec, flags)
+        s = L.Sim(p)
+        s.init(*init)
+        s.step(60)
+        d = s.derived
+        runs[name] = conc(*s.fields(), d.rho_l, d.rho_g)
+        assert s.observe()["n_bad"] == 0
+        s.close()
+    e_imp = float(np.abs(runs["imp"] - runs["fp64"]).max())
+    e_sto = float(np.abs(runs["stored"] - runs["fp64"]).max())
+    say("fp16 storage", kind, "implicit g", e_imp, "stored g", e_sto)
+    assert e_imp <= 2e-3 and e_sto <= 2e-3
+    assert e_imp <= e_sto + 1e-4
+
+
+def test_reinit_after_implicit_steps():
+    """Initialising a handle again after implicit-g steps starts from the
+    stored g of the new initial state (the same run as a fresh handle)."""
+    p, init = case("walled", L.FP32)
+    s = L.Sim(p)
+    s.init(*init)
+    s.step(9)
+    s.init(*init)
+    s.step(5)
+    a = s.fields() + s.pops()
+    s.close()
+    t = L.Sim(p)
+    t.init(*init)
+    t.step(5)
+    b = t.fields() + t.pops()
+    t.close()
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)

@@ -24,8 +24,9 @@ G = (0.01, 0.012, 0.009)
 
 
 def mixed_cases():
-    """Six simulations over every batch class: 2D 62-node tiles in three
-    precisions, a periodic 2D box, 3D FP32 and FP64 (ghost-layer launch)."""
+    """Seven simulations over every batch class: 2D 62-node tiles in three
+    precisions, a periodic 2D box, 3D in FP32, FP64 and FP16 storage
+    (ghost-layer launch, implicit g)."""
     return [
         (L.make_params(L.D2Q9, (96, 48), gamma=G, theta_deg=60.0, precision=L.FP64),
          I.sessile_drop_2d(96, 48, 16)),
@@ -39,6 +40,8 @@ def mixed_cases():
          I.sessile_drop_3d(40, 24, 20, 8)),
         (L.make_params(L.D3Q27, (24, 24, 16), gamma=G, theta_deg=110.0, precision=L.FP64),
          I.sessile_drop_3d(24, 24, 16, 6)),
+        (L.make_params(L.D3Q27, (28, 20, 14), gamma=G, theta_deg=100.0, precision=L.FP16S),
+         I.sessile_drop_3d(28, 20, 14, 6)),
     ]
 
 
@@ -88,7 +91,7 @@ def test_server_results_equal_runs_alone_and_fit_the_pool():
     time; every result equals its run alone, and the simulations resident at
     any moment fit in the pool."""
     cases = mixed_cases()
-    steps = [23, 40, 17, 31, 12, 9]
+    steps = [23, 40, 17, 31, 12, 9, 14]
     need = [L.server_request_bytes(p) for p, _ in cases]
     pool = int(sum(sorted(need)[-3:]) + 2 * (1 << 20) + max(1 << 20, sum(need) // 256))
     srv = L.Server(pool, max_resident=8, max_skips=2)
