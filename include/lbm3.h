@@ -108,6 +108,10 @@ typedef struct {
                                (0: 1e-3 FP64, 1e-2 FP32 arithmetic) */
     double  alpha_tol;      /* Newton tolerance (0: 1e-10 FP64, 1e-5 FP32) */
     int32_t alpha_maxit;    /* Newton iteration cap (0: 20) */
+    double  detect_ratio;   /* geometric wetting, interface detection (Sec. IV B):
+                               a wall node is on the 2-3 interface when
+                               |grad_par rho| chi < detect_ratio (rho_l - rho_g)
+                               |grad_par phi| (0: the paper's 0.01) */
 } lbm3_params;
 
 /* Values the library derives from lbm3_params (lbm3_resolve). */

@@ -562,7 +562,8 @@ static int classify(const or_params *p, double ngr, double ngp, double dot,
 {
     double drho = p->rho_l - p->rho_g;
     int k;
-    if (ngr * p->chi < 0.01 * drho * ngp) k = 2;
+    const double ratio = p->detect_ratio > 0.0 ? p->detect_ratio : 0.01;
+    if (ngr * p->chi < ratio * drho * ngp) k = 2;
     else if (dot < 0.0) k = 1;
     else k = 0;
     if (r > 0.5 * p->rho_l && ph < -0.95 * p->chi) k = 1;

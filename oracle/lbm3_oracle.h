@@ -46,6 +46,8 @@ typedef struct {
     int    alpha_maxit;
     int    no_collide;     /* 1: streaming and bounce-back only */
     int    force_alpha2;   /* 1: alpha = 2 everywhere (plain BGK with 1/tau = 2 beta) */
+    double detect_ratio;   /* first interface-detection rule (Sec. IV B): the 2-3 interface
+                              when |grad rho| chi < detect_ratio drho |grad phi| (0: 0.01) */
     int    wall_par;       /* first-layer tangential derivatives of the force: 0 in-layer
                               central differences, 1 the bulk stencil with the links that
                               point into the wall mirrored to the fluid side (Sec. IV) */

@@ -33,7 +33,8 @@ class OrParams(C.Structure):
         ("kw", (C.c_double * 2) * 2),
         ("alpha_eps", C.c_double), ("alpha_tol", C.c_double),
         ("alpha_maxit", C.c_int),
-        ("no_collide", C.c_int), ("force_alpha2", C.c_int), ("wall_par", C.c_int),
+        ("no_collide", C.c_int), ("force_alpha2", C.c_int), ("detect_ratio", C.c_double),
+        ("wall_par", C.c_int),
     ]
 
 
@@ -180,7 +181,7 @@ def make_params(D, n, *, rho_l=1.0, rho_g=1e-3, lam=(0.0625, 0.03, 0.03),
                 kap=(0.03, 0.03, 0.03), chi=5.0, tau_f=1.0, tau_g=1.0, Gamma=1.0,
                 walls=True, wetting=GEOM_INTERP, theta_deg=90.0, kw=((0, 0), (0, 0)),
                 alpha_eps=1e-3, alpha_tol=1e-10, alpha_maxit=20, no_collide=False,
-                force_alpha2=False, eos=None, wall_par=0):
+                force_alpha2=False, eos=None, wall_par=0, detect_ratio=0.0):
     """Oracle parameters.  beta = 1/(2 tau_f) (nu = (1/beta - 1)/6, Sec. II C).
     theta_deg: scalar, (theta21, theta31, theta23) or a 2x3 per-wall table."""
     p = OrParams()
@@ -211,6 +212,7 @@ def make_params(D, n, *, rho_l=1.0, rho_g=1e-3, lam=(0.0625, 0.03, 0.03),
     p.no_collide = int(no_collide)
     p.force_alpha2 = int(force_alpha2)
     p.wall_par = int(wall_par)
+    p.detect_ratio = detect_ratio
     return p
 
 

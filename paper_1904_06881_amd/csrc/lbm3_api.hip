@@ -249,6 +249,7 @@ lbm3_status lbm3_create(const lbm3_params *p, void *ws, size_t bytes, void *stre
     k.alpha_eps = p->alpha_eps > 0 ? p->alpha_eps : (p->precision == LBM3_FP64 ? 1e-3 : 1e-2);
     k.alpha_tol = p->alpha_tol > 0 ? p->alpha_tol : (p->precision == LBM3_FP64 ? 1e-10 : 1e-5);
     k.alpha_maxit = p->alpha_maxit > 0 ? p->alpha_maxit : 20;
+    k.detect_ratio = p->detect_ratio > 0 ? p->detect_ratio : 0.01;
     k.flags = p->flags;
     char *base = (char *)ws;
     Buffers &b = h->b;

@@ -23,6 +23,7 @@ struct KParams {
     double kw[2][2];             // per wall: kappa_rho^w, kappa_phi^w
     double alpha_eps, alpha_tol;
     int alpha_maxit;
+    double detect_ratio;         // first interface-detection rule's threshold
     unsigned flags;              // 1 no-collide, 2 alpha = 2, 4 one fused kernel in 3D
 };
 

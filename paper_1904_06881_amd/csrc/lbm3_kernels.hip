@@ -914,10 +914,10 @@ k_moments_batch(const SimDesc *__restrict__ d, const int *__restrict__ sim, int 
 // Interface detection (paper's rules, cascade 1-3 then 4-5 override):
 // 0 = 1-2 (theta21), 1 = 1-3 (theta31), 2 = 2-3 (theta23).
 template <typename R>
-__device__ __forceinline__ int classify(R ngr, R ngp, R dot, R r, R ph, R rho_l, R drho, R chi)
+__device__ __forceinline__ int classify(R ngr, R ngp, R dot, R r, R ph, R rho_l, R drho, R chi, R ratio)
 {
     int k;
-    if (ngr * chi < (R)0.01 * drho * ngp) k = 2;
+    if (ngr * chi < ratio * drho * ngp) k = 2;
     else if (dot < (R)0) k = 1;
     else k = 0;
     if (r > (R)0.5 * rho_l && ph < (R)-0.95 * chi) k = 1;
@@ -1024,7 +1024,7 @@ __device__ __forceinline__ void ghost_value(const KParams &kp, const R (&cot)[3]
     R ngp = sqrt(gp[0] * gp[0] + gp[1] * gp[1]);
     if (ngr < (R)1e-12 * drho && ngp < (R)1e-12 * drho) return;
     R dot = gr[0] * gp[0] + gr[1] * gp[1];
-    int cls = classify(ngr, ngp, dot, r0, p0, (R)kp.rho_l, drho, chi);
+    int cls = classify(ngr, ngp, dot, r0, p0, (R)kp.rho_l, drho, chi, (R)kp.detect_ratio);
     const R ct = cls == 0 ? cot[0] : (cls == 1 ? cot[1] : cot[2]);
     const R *gc = cls == 2 ? gp : gr;
     R ngc = cls == 2 ? ngp : ngr;

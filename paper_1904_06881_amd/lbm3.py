@@ -32,7 +32,7 @@ class lbm3_params(C.Structure):
         ("tau_g", C.c_double), ("Gamma", C.c_double), ("wetting", C.c_int32),
         ("theta_deg", (C.c_double * 3) * 2), ("kw", (C.c_double * 2) * 2),
         ("precision", C.c_int32), ("flags", C.c_uint32), ("alpha_eps", C.c_double),
-        ("alpha_tol", C.c_double), ("alpha_maxit", C.c_int32),
+        ("alpha_tol", C.c_double), ("alpha_maxit", C.c_int32), ("detect_ratio", C.c_double),
     ]
 
 
@@ -145,7 +145,7 @@ def _dp(a):
 def make_params(lattice, n, *, walls=True, rho_l=1.0, rho_g=1e-3, lam=None, kap=None,
                 gamma=None, width=4.0, chi=5.0, tau_f=1.0, tau_g=1.0, Gamma=1.0,
                 wetting=WET_GEOM_INTERP, theta_deg=90.0, kw=((0, 0), (0, 0)), precision=FP64,
-                flags=0, alpha_eps=0.0, alpha_tol=0.0, alpha_maxit=0):
+                flags=0, alpha_eps=0.0, alpha_tol=0.0, alpha_maxit=0, detect_ratio=0.0):
     """Fill lbm3_params.  Give lam/kap (native) or gamma=(g12, g13, g23) with
     width.  theta_deg: scalar, (theta21, theta31, theta23) or a 2x3 table."""
     p = lbm3_params()
@@ -178,6 +178,7 @@ def make_params(lattice, n, *, walls=True, rho_l=1.0, rho_g=1e-3, lam=None, kap=
     p.precision = precision
     p.flags = flags
     p.alpha_eps, p.alpha_tol, p.alpha_maxit = alpha_eps, alpha_tol, alpha_maxit
+    p.detect_ratio = detect_ratio
     return p
 
 

@@ -24,7 +24,8 @@ def oracle_params_from(p, d):
                          alpha_eps=p.alpha_eps or 1e-3,
                          alpha_tol=p.alpha_tol or (1e-10 if p.precision == 0 else 1e-5),
                          alpha_maxit=p.alpha_maxit or 20,
-                         no_collide=bool(p.flags & 1), force_alpha2=bool(p.flags & 2), eos=eos)
+                         no_collide=bool(p.flags & 1), force_alpha2=bool(p.flags & 2), eos=eos,
+                         detect_ratio=p.detect_ratio)
 
 
 def conc(rho, phi, rho_l, rho_g, chi=5.0):

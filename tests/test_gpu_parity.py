@@ -71,13 +71,14 @@ def test_fp64_2000_steps_cfg1():
 
 
 @pytest.mark.parametrize("case", ["force", "extrap", "periodic", "ragged", "asym_random", "high_wall",
-                                  "steep_random"])
+                                  "steep_random", "detect_ratio"])
 def test_fp64_variants(case):
     """FP64 parity over 40 steps on the other code paths: force method with
     wall forces, geometric extrapolation, fully periodic, a ragged grid, three
     components with kappa2 != kappa3 on random fields, angles that differ per
-    wall and interface, and steep angles whose interpolation points lie beyond
-    the LDS halo (read from the fields in memory)."""
+    wall and interface, steep angles whose interpolation points lie beyond
+    the LDS halo (read from the fields in memory), and a liquid-liquid
+    drop with the detection threshold raised to 0.1."""
     steps = 40
     if case == "force":
         rho0, phi0 = I.sessile_drop_2d(64, 40, 12, xc=32)
@@ -99,6 +100,12 @@ def test_fp64_variants(case):
         rho0, phi0 = I.random_fields((30, 70), seed=23)
         p = L.make_params(L.D2Q9, (70, 30), gamma=(0.01, 0.01, 0.01), width=4.0,
                           theta_deg=[[20, 160, 25], [155, 22, 158]])
+    elif case == "detect_ratio":
+        x, y = np.mgrid[0:40, 0:80][1].astype(float), np.mgrid[0:40, 0:80][0].astype(float)
+        sh = I.profile(14.0 - np.sqrt((x - 40.0) ** 2 + (y - 0.5) ** 2), 4.0)
+        rho0, phi0 = I.fields_from_conc(sh, 1.0 - sh)
+        p = L.make_params(L.D2Q9, (80, 40), gamma=(0.01, 0.01, 0.01), width=4.0, theta_deg=(90.0, 90.0, 120.0),
+                          detect_ratio=0.1)
     elif case == "asym_random":
         rho0, phi0 = I.random_fields((30, 50), seed=11)
         p = L.make_params(L.D2Q9, (50, 30), lam=(0.07, 0.04, 0.02), kap=(0.03, 0.05, 0.012),

@@ -41,11 +41,11 @@ def lin_periodic(row, pos):
     return (1.0 - t) * row[i0 % n] + t * row[(i0 + 1) % n]
 
 
-def ghost_2d(rho0, phi0, wetting=O.GEOM_INTERP, theta=THETA):
+def ghost_2d(rho0, phi0, wetting=O.GEOM_INTERP, theta=THETA, detect_ratio=0.0):
     """Oracle state after init on a grid uniform along y: (first fluid layer
     rho, phi) and (ghost layer rho, phi) of the bottom wall."""
     ny, nx = rho0.shape
-    po = O.make_params(2, (nx, ny), wetting=wetting, theta_deg=theta)
+    po = O.make_params(2, (nx, ny), wetting=wetting, theta_deg=theta, detect_ratio=detect_ratio)
     s = O.Sim(po)
     s.init(rho0, phi0)
     r, ph = s.fields()
@@ -72,10 +72,10 @@ def tanh_row(nx, x0):
     return 0.5 * (1.0 + np.tanh(2.0 * (x - x0) / W))
 
 
-def check_class(rrow, prow, i, k):
+def check_class(rrow, prow, i, k, detect_ratio=0.0):
     """The oracle's ghost value at node i is that of class k, and the other
     two classes would have given values at least 1e-4 away."""
-    (r1, p1), (rg, pg) = ghost_2d(*rows_to_grid(rrow, prow))
+    (r1, p1), (rg, pg) = ghost_2d(*rows_to_grid(rrow, prow), detect_ratio=detect_ratio)
     want = expected_interp_2d(r1, p1, i, k)
     assert abs(rg[i] - want[0]) < 1e-12 and abs(pg[i] - want[1]) < 1e-12
     for other in range(3):
@@ -113,6 +113,17 @@ def test_rule1_threshold_on_gradient_ratio():
     for factor, k in ((0.5, 2), (2.0, 0)):
         rho = 0.9 + factor * 0.01 * DRHO / CHI * phi
         check_class(rho, phi, 16, k)
+
+
+@pytest.mark.parametrize("factor,k", [(2.0, 2), (5.0, 2), (20.0, 0)])
+def test_rule1_threshold_is_a_parameter(factor, k):
+    """The threshold of rule 1 as a parameter (detect_ratio 0.1 in place of
+    the printed 0.01): a density gradient of 2x or 5x the printed ratio now
+    still gives 2-3, one of 20x (2x the new threshold) the liquid-gas class."""
+    s = tanh_row(32, 15.7)
+    phi = CHI * (2.0 * s - 1.0)
+    rho = 0.9 + factor * 0.01 * DRHO / CHI * phi
+    check_class(rho, phi, 16, k, detect_ratio=0.1)
 
 
 def test_rule4_overrides_toward_13():
