@@ -347,7 +347,7 @@ def main():
                     help="only run a plain 256 MiB device copy (HBM counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs each simulation on a single device "
+        print("bench.py measures one GPU: the library runs each simulation on a single device "
               "(--gpus %d is not supported)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 

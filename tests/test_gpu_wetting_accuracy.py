@@ -13,8 +13,8 @@ Measured (interpolation / extrapolation, degrees): 30: 33.0 / 30.9;
 methods within 1 degree in [60, 120] and interpolation the more accurate
 outside that range.  Here interpolation is the more accurate on the
 hydrophobic side (120 and 135 degrees) and extrapolation on the hydrophilic
-side (30 and 45); both carry the 1.5-3 degree liquid-gas bias of this
-build's ideal-force discretisation (the liquid-liquid and oracle pins show
+side (30 and 45); both carry the 1.5-3 degree liquid-gas bias of the
+link-pressure ideal force (the liquid-liquid and oracle pins show
 the boundary itself sets the angle).  Passing checks: the angle follows
 theta monotonically over [30, 135] for both methods, both are within 2
 degrees at 60 and 90, and interpolation is the closer one at 120 and 135.
