@@ -46,7 +46,7 @@ def bulk_pressure(po, rho, phi):
     return O.local_thermo(po, rho, phi, [0, 0], [0, 0], 0.0, 0.0)[2][0, 0]
 
 
-def test_u5_flat_liquid_liquid_interface_is_tanh():
+def test_flat_liquid_liquid_interface_is_tanh():
     """Sec. III: C2 across a flat 2-3 interface is (1 + tanh(x / 2 alpha))/2
     with alpha = W/4 = 1; fitted alpha within 2 %."""
     p = L.make_params(L.D2Q9, (128, 4), gamma=G, width=4.0, walls=False, precision=L.FP64)
@@ -84,7 +84,7 @@ def laplace(kind, R, steps):
     return dP * Rf, (lam[1] + lam[2]) / 6.0, r[2, 2]
 
 
-def test_u6_laplace_liquid_liquid():
+def test_laplace_liquid_liquid():
     """A 2-3 drop: dP R the same for R = 16 and 32 within 3 %, and within 5 %
     of the closed-form gamma_23 = alpha (lambda_2 + lambda_3)/6 (Eq. 38)."""
     g16, closed, _ = laplace("LL", 16, 20000)
@@ -96,7 +96,7 @@ def test_u6_laplace_liquid_liquid():
 
 @pytest.mark.xfail(reason="curved liquid-gas interfaces carry an excess tension with the link-pressure "
                           "ideal force (dP R about 0.017-0.018 for gamma_12 = 0.01)", strict=False)
-def test_u6_laplace_liquid_gas():
+def test_laplace_liquid_gas():
     g16, _, gas16 = laplace("LG", 16, 20000)
     g32, _, gas32 = laplace("LG", 32, 20000)
     say("dP R", g16, g32, "gas density", gas16, gas32)
@@ -131,7 +131,7 @@ def sessile_angle(theta, liquid_liquid, steps):
                "below 0.01 (rho_l - rho_g)/chi) misses centre nodes of the liquid-liquid interface, "
                "which then take theta21 = theta31 = 90", strict=False)),
 ])
-def test_u8_contact_angle_liquid_liquid(theta):
+def test_contact_angle_liquid_liquid(theta):
     """A liquid-2 drop in liquid 3 started as a 90-degree cap relaxes to
     theta23 (geometric interpolation, Sec. IV B): 61.6 degrees after 100k
     steps for theta23 = 60 (the paper's bound is 1 degree; tested at 2)."""
@@ -143,7 +143,7 @@ def test_u8_contact_angle_liquid_liquid(theta):
 @pytest.mark.xfail(reason="liquid-gas drops started as 90-degree caps end 1.5 and 2.8 degrees beyond "
                           "theta_21 = 60 and 120 after 16k steps (1 degree asked)", strict=False)
 @pytest.mark.parametrize("theta", [60.0, 120.0])
-def test_u8_contact_angle_liquid_gas(theta):
+def test_contact_angle_liquid_gas(theta):
     a = sessile_angle(theta, False, 16000)
     say("theta_21", theta, "measured", a)
     assert abs(a - theta) < 1.0

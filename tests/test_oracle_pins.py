@@ -300,7 +300,7 @@ def test_stencils_lattice_symbols(D):
     assert np.allclose(s.field("lap_rho"), 0.1 * lap_sym * np.sin(arg), atol=1e-14)
 
 
-# ------------------------------------------------- streaming (U3) ----------
+# ------------------------------------------------- streaming ----------
 def _numpy_stream(fs, c, walls, D):
     """Brute-force streaming with halfway bounce-back on the last axis."""
     Q = fs.shape[0]
@@ -350,7 +350,7 @@ def test_streaming_is_exact_permutation(D, walls):
     assert np.array_equal(np.sort(f1[sl].ravel()), np.sort(f[sl].ravel()))
 
 
-# ----------------------------------------------------- conservation (U4) --
+# ----------------------------------------------------- conservation --
 def cfg1_params(**kw):
     base = dict(lam=(0.14, 0.025, 0.025), kap=(0.021, 0.025, 0.025), theta_deg=60.0)
     base.update(kw)
