@@ -7,8 +7,7 @@ contact angle theta = theta21 = theta31 = theta23 on every interface
 unbalance of Eq. (capillaryforce) is Delta gamma = gamma23 cos theta, the
 drive 2 Delta gamma; a Poiseuille slug of viscosity nu then moves at
 v_inf = H Delta gamma / (6 rho_l nu L) after a relaxation time
-tau = H^2 / (12 nu) (Eqs. bislugvelocity, bislugrelaxation,
-centreofmassposition).
+tau = H^2 / (12 nu) (Eqs. 60-62).
 
 The paper finds the closed form in the limit of long trains and, for
 finite trains, explains the extra dissipation by the dynamic contact
@@ -181,7 +180,7 @@ def test_bislug_speed_follows_the_dynamic_angle_model(theta):
                           "is below the static-angle closed form, which holds only for L >> H", strict=False)
 def test_bislug_closed_form_static_angles():
     """The closed form with the static angles (theta = 60 degrees, L = 1500):
-    centre-of-mass trajectory fitted with Eq. (centreofmassposition) after the
+    centre-of-mass trajectory fitted with Eq. 62 after the
     first 1000 steps, v within 10 % of v_inf and tau within 50 % of
     H^2 / (12 nu)."""
     ts, xs, r, ph, d = run_train(1500, 60.0, 24000, 200)

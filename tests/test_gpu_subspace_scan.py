@@ -10,7 +10,7 @@ simulations stepped together by lbm3_step_batch, FP64.
 Checks (what the paper states about this subspace): gamma23 follows the
 closed form alpha23 (lambda2 + lambda3)/6 (Eq. 38; alpha23 = 1 here)
 within 5 %; the deformation coefficient of the liquid-liquid interface
-(Eq. QFdef: max - min of the minority concentration C1 within 4 nodes of
+(Eq. 39: max - min of the minority concentration C1 within 4 nodes of
 it) is near zero, read as below 0.05 on a map where the paper's D2 and D3
 reach 0.25, and D2, D3 of the liquid-gas interfaces stay below 0.3; gamma12
 grows with X and gamma13 with Y; the Neumann angles of every point are

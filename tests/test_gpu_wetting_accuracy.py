@@ -2,8 +2,8 @@
 started as 90-degree caps (R = 30 on a 240 x 110 channel, gamma = 0.01,
 density ratio 1000, 20000 steps, FP64) relax toward the prescribed angle;
 the measured angle (circle fit, 2W excluded) is tabulated for geometric
-interpolation (Eq. interp2D) and geometric extrapolation (Eqs. geomamgle,
-geomding) at theta in {30, 45, 60, 90, 120, 135, 150} degrees, the
+interpolation (Eq. 47) and geometric extrapolation (Eqs. 45,
+46) at theta in {30, 45, 60, 90, 120, 135, 150} degrees, the
 comparison of the paper's sessile-drop study.  All 14 drops run as one
 batch (lbm3_step_batch).
 

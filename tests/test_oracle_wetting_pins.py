@@ -4,11 +4,11 @@ test computes by hand from the paper's rules and formulas:
 * the interface-detection rules (one constructed first-layer state per rule,
   with distinct theta21, theta31, theta23 so that every class leads to a
   different ghost value);
-* the direction of the geometric-interpolation shift (Eq. interp2D) and, in
-  3D, the support of the planar interpolation (Eq. interp3D): the triangle of
+* the direction of the geometric-interpolation shift (Eq. 47) and, in
+  3D, the support of the planar interpolation (Eqs. 48-49): the triangle of
   the unit cell that contains the interpolation point, on a bilinear field
   where the other triangles give other values;
-* geometric extrapolation (Eqs. geomamgle and geomding) per field along the
+* geometric extrapolation (Eqs. 45 and 46) per field along the
   in-plane direction of grad c, in 2D and 3D;
 * the same rules in the dynamics: a liquid-3 drop in gas goes to theta31 (not
   theta21), and extrapolation drives a 90-degree cap toward theta21.
@@ -150,7 +150,7 @@ def test_uniform_first_layer_is_copied():
 
 
 def test_extrapolation_2d_per_field():
-    """Eqs. geomamgle and geomding: q_ghost = q + cot(theta) (dq/dx) m, m the
+    """Eqs. 45 and 46: q_ghost = q + cot(theta) (dq/dx) m, m the
     sign of dc/dx (c = rho at the gas-liquid-2 interface, theta21 = 60), so
     the ghost is more liquid than the first layer for theta < 90."""
     s = tanh_row(32, 15.7)
@@ -218,7 +218,7 @@ def plane_value(q, corners, lx, ly):
 
 
 def test_interpolation_3d_uses_the_triangle_containing_the_point():
-    """Eq. interp3D on the triangle of the unit cell that contains the point
+    """Eqs. 48-49 on the triangle of the unit cell that contains the point
     (cot theta21) m, m the in-plane unit direction of grad rho: the three
     corners nearest to it.  The literal three corners furthest from the node
     give a different value on this bilinear field."""
