@@ -4,7 +4,7 @@ holding a train of two liquid slugs of equal length (liquid 2, then liquid
 3; L = L1 + L2) with 200 lattice units of gas on each side, and the same
 contact angle theta = theta21 = theta31 = theta23 on every interface
 (geometric interpolation).  With gamma12 = gamma13 the surface tension
-unbalance of Eq. (capillaryforce) is Delta gamma = gamma23 cos theta, the
+unbalance of Eq. 54 is Delta gamma = gamma23 cos theta, the
 drive 2 Delta gamma; a Poiseuille slug of viscosity nu then moves at
 v_inf = H Delta gamma / (6 rho_l nu L) after a relaxation time
 tau = H^2 / (12 nu) (Eqs. 60-62).
