@@ -178,6 +178,7 @@ def other_grids(L, I):
 # burst measured.  A burst of 48 small D2Q9 grids (64^2..256^2) is timed
 # beside it.
 SERVE_N, SERVE_STEPS, SERVE_QUANTUM, SERVE_LOAD = 48, (250, 1000), 50, 0.8
+SERVE_DIV = 20   # the configured 5k..20k steps per request, divided
 SERVE_POOL = 24 << 30
 
 
@@ -216,6 +217,8 @@ def run_serving(L, reqs):
         nr, nq = srv.run(SERVE_QUANTUM)
         for r in srv.poll():
             done[r["tag"]] = r
+            if len(done) % 64 == 0:
+                print("serving: %d/%d batched requests done" % (len(done), n), file=sys.stderr, flush=True)
         if nr == 0 and nq == 0 and i < n and len(done) == i:
             time.sleep(max(0.0, reqs[i]["arrival"] - (srv.clock() - t0)))
     makespan = max(r["t_done"] for r in done.values()) - t0
@@ -243,6 +246,8 @@ def run_plain(L, reqs):
         del s
         ok += o["status"] == 0
         lat.append(time.perf_counter() - t0 - q["arrival"])
+        if len(lat) % 64 == 0:
+            print("serving: %d/%d requests done one at a time" % (len(lat), len(reqs)), file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     return lat, time.perf_counter() - t0, ok
 
@@ -250,7 +255,9 @@ def run_plain(L, reqs):
 def _compare(L, reqs):
     total = sum(q["updates"] for q in reqs)
     lat_s, span_s, ok_s = run_serving(L, reqs)
+    print("serving: %d requests batched in %.1f s" % (len(reqs), span_s), file=sys.stderr, flush=True)
     lat_p, span_p, ok_p = run_plain(L, reqs)
+    print("serving: %d requests one at a time in %.1f s" % (len(reqs), span_p), file=sys.stderr, flush=True)
     return {
         "node_updates": total,
         "batched": {"MLUPS": total / span_s / 1e6, "makespan_s": span_s, "p50_s": _pct(lat_s, 50),
@@ -274,7 +281,7 @@ def serving_leg(L, I):
     stream = _compare(L, reqs)
     desc = ("%d requests of the configuration-5 distribution (seed 2024): 70%% D2Q9 64^2..1024^2, 30%% D3Q27 "
             "64^3..192^3, sessile drops theta 30..150 deg, gamma 0.005..0.03, FP32 / FP16-offset storage, "
-            "%d..%d steps (the configured 5k..20k / 20)" % (SERVE_N, SERVE_STEPS[0], SERVE_STEPS[1]))
+            "%d..%d steps (the configured 5k..20k / %d)" % (SERVE_N, SERVE_STEPS[0], SERVE_STEPS[1], SERVE_DIV))
     burst["workload"] = desc + ", all arriving together"
     stream["workload"] = desc + (", Poisson arrivals (seed 2026) at %.2f/s = %.1f x the sequential capacity "
                                  "measured on the burst" % (rate, SERVE_LOAD))
@@ -330,6 +337,7 @@ def cpu_baseline():
 
 
 def main():
+    global SERVE_N, SERVE_STEPS, SERVE_DIV
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
@@ -340,12 +348,19 @@ def main():
     ap.add_argument("--no-other", action="store_true", help="skip the D2Q9 channel workloads")
     ap.add_argument("--precision", default="fp32", choices=("fp32", "fp16s", "fp64"),
                     help="storage of the timed run (the headline is fp32)")
+    ap.add_argument("--serve-requests", type=int, default=SERVE_N,
+                    help="requests of the serving comparison (the configuration asks 512)")
+    ap.add_argument("--serve-step-div", type=int, default=20,
+                    help="divide the configured 5k..20k steps per request by this (1: the full counts)")
     ap.add_argument("--serve-profile", action="store_true",
                     help="only run the serving burst (batched, then plain) and print the phase clocks; for a "
                          "kernel trace of the two")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 256 MiB device copy (HBM counter calibration) and exit")
     args = ap.parse_args()
+    SERVE_N = args.serve_requests
+    SERVE_DIV = args.serve_step_div
+    SERVE_STEPS = (5000 // args.serve_step_div, 20000 // args.serve_step_div)
     if args.gpus != 1:
         print("bench.py measures one GPU: the library runs each simulation on a single device "
               "(--gpus %d is not supported)" % args.gpus, file=sys.stderr)
