@@ -357,6 +357,9 @@ def main():
                          "kernel trace of the two")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 256 MiB device copy (HBM counter calibration) and exit")
+    ap.add_argument("--hbm-rate", action="store_true",
+                    help="only time torch's own 2 GiB device copy and fill (an attainable HBM rate to set the "
+                         "kernels' rates beside) and exit")
     args = ap.parse_args()
     SERVE_N = args.serve_requests
     SERVE_DIV = args.serve_step_div
@@ -390,6 +393,28 @@ def main():
         y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4}), flush=True)
+        return
+
+    if args.hbm_rate:
+        x = torch.ones(1 << 29, dtype=torch.float32, device="cuda:0")
+        y = torch.empty_like(x)
+        nb = x.numel() * 4
+
+        def timed(fn, reps=20):
+            fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / reps / 1e3
+
+        tc = timed(lambda: y.copy_(x))
+        tf = timed(lambda: y.fill_(2.0))
+        print(json.dumps({"bytes": nb, "copy_ms": tc * 1e3, "copy_TBs": 2 * nb / tc / 1e12,
+                          "fill_ms": tf * 1e3, "fill_TBs": nb / tf / 1e12}), flush=True)
         return
 
     precs = {"fp32": (L.FP32, 4, 4, False), "fp16s": (L.FP16S, 2, 4, True), "fp64": (L.FP64, 8, 8, False)}
