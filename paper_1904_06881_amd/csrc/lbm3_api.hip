@@ -119,21 +119,23 @@ Layout layout(const lbm3_params *p)
     int D = lattice_D(p->lattice);
     int Q = D == 2 ? 9 : 27;
     long long N = (long long)p->n[0] * p->n[1] * (D == 2 ? 1 : p->n[2]);
+    // every array of a block QS elements after the previous one, every field QS long
+    const long long QS = lbm3k::array_stride(N);
     size_t s = p->precision == LBM3_FP64 ? 8 : (p->precision == LBM3_FP32 ? 4 : 2);
     size_t r = p->precision == LBM3_FP64 ? 8 : 4;
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
-    for (int k = 0; k < 2; ++k) L.f[k] = take((size_t)Q * N * s);
+    for (int k = 0; k < 2; ++k) L.f[k] = take((size_t)Q * QS * s);
     // implicit g: nothing writes a second g set (the collision stores the
     // five g^eq values; g is written only by the initialisation and by
     // exports, each into the current set), so both parities share one
-    if (implicit_g(p)) L.g[0] = L.g[1] = take((size_t)Q * N * s);
+    if (implicit_g(p)) L.g[0] = L.g[1] = take((size_t)Q * QS * s);
     else
-        for (int k = 0; k < 2; ++k) L.g[k] = take((size_t)Q * N * s);
-    for (int k = 0; k < 2; ++k) L.rho[k] = take((size_t)N * r);
-    for (int k = 0; k < 2; ++k) L.phi[k] = take((size_t)N * r);
-    L.fmu = D == 3 ? take((size_t)(D + 1) * N * r) : 0;  // F, mu_phi of the two-kernel step
-    L.gp = implicit_g(p) ? take((size_t)5 * N * r) : 0;    // (a, phi, v) of g^eq
+        for (int k = 0; k < 2; ++k) L.g[k] = take((size_t)Q * QS * s);
+    for (int k = 0; k < 2; ++k) L.rho[k] = take((size_t)QS * r);
+    for (int k = 0; k < 2; ++k) L.phi[k] = take((size_t)QS * r);
+    L.fmu = D == 3 ? take((size_t)(D + 1) * QS * r) : 0;  // F, mu_phi of the two-kernel step
+    L.gp = implicit_g(p) ? take((size_t)5 * QS * r) : 0;    // (a, phi, v) of g^eq
     L.scratch = take((size_t)N * 8);
     L.counters = take(counter_slots(p) * lbm3k::kCntStride * sizeof(unsigned long long));
     L.partials = take((size_t)1024 * 16 * sizeof(double));
@@ -228,6 +230,7 @@ lbm3_status lbm3_create(const lbm3_params *p, void *ws, size_t bytes, void *stre
     k.nw = D == 2 ? k.ny : k.nz;
     k.walls = p->walls ? 1 : 0;
     k.N = (long long)k.nx * k.ny * k.nz;
+    k.QS = lbm3k::array_stride(k.N);
     k.PS = D == 2 ? k.nx : (long long)k.nx * k.ny;
     k.rho_l = d.rho_l;
     k.rho_g = d.rho_g;
@@ -289,7 +292,7 @@ lbm3_status lbm3_init(lbm3 *h, const double *rho0, const double *phi0)
     hipError_t e;
     // populations of the ghost layers are never read by a step; zeroing both
     // buffers keeps exported arrays deterministic
-    size_t pop_bytes = (size_t)k.Q * k.N * (h->prec == LBM3_FP64 ? 8 : (h->prec == LBM3_FP32 ? 4 : 2));
+    size_t pop_bytes = (size_t)k.Q * k.QS * (h->prec == LBM3_FP64 ? 8 : (h->prec == LBM3_FP32 ? 4 : 2));
     for (int i = 0; i < 2; ++i)
         if ((e = hipMemsetAsync(h->b.f[i], 0, pop_bytes, h->stream)) != hipSuccess ||
             (e = hipMemsetAsync(h->b.g[i], 0, pop_bytes, h->stream)) != hipSuccess)

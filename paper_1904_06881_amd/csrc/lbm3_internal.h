@@ -13,6 +13,7 @@ struct KParams {
     int walls;           // 1: ghost layers at 0 and nw-1 of the last axis
     long long N;         // nodes
     long long PS;        // plane stride of the last axis (nx or nx*ny)
+    long long QS;        // elements from one array of a block to the next (array_stride(N))
     double rho_l, rho_g, drho, chi;
     double a, b, T, C, psi0;
     double lam1, lam2, lam3;
@@ -47,6 +48,20 @@ inline long long small2d_block_slots(int D, long long nx, long long nw)
 }
 
 enum Prec { P64 = 0, P32 = 1, P16 = 2 };
+
+// Element stride between consecutive arrays of one block (the Q populations
+// of a set, the force components, the five g^eq values) and the size of each
+// field array: N rounded up to 64 nodes, plus 544 when that is a multiple of
+// 16384.  Arrays a large power of two apart (256^3 FP32: 127 x 512 KiB) start
+// on the same memory channels, and 27 or 54 of them streamed together then
+// read at 5.1 TB/s and push-copy at 3.8; 544 nodes further apart they reach
+// 6.2 and 4.6, the rates of grids whose size is not such a multiple.
+inline long long array_stride(long long N)
+{
+    long long q = (N + 63) / 64 * 64;
+    if (q % 16384 == 0) q += 544;
+    return q;
+}
 
 // Device buffers of one simulation, carved out of the caller's workspace.
 struct Buffers {

@@ -584,8 +584,8 @@ __device__ __forceinline__ void moments_nodes(const KParams &kp, const typename 
     VS fv[Q], gv[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        fv[i] = *(const VS *)(f + (long long)i * kp.N + n);
-        gv[i] = *(const VS *)(g + (long long)i * kp.N + n);
+        fv[i] = *(const VS *)(f + (long long)i * kp.QS + n);
+        gv[i] = *(const VS *)(g + (long long)i * kp.QS + n);
     }
     VR r = (R)0, ph = (R)0;
 #pragma unroll
@@ -698,6 +698,7 @@ __device__ __forceinline__ void moments_imp_tile(const KParams &kp, const typena
     const int nx = kp.nx, ny = kp.ny, nw = kp.nw;
     const bool walls = kp.walls != 0;
     const unsigned N = (unsigned)kp.N, PS = (unsigned)kp.PS;
+    const unsigned QS = (unsigned)kp.QS;
     const int ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY;
     const int tx = (int)(b % (unsigned)ntx), ty = (int)((b / (unsigned)ntx) % (unsigned)nty);
     const int p = (int)(b / (unsigned)(ntx * nty)) + (walls ? 1 : 0);
@@ -716,7 +717,7 @@ __device__ __forceinline__ void moments_imp_tile(const KParams &kp, const typena
             if (!walls) gz = gz < 0 ? gz + nw : (gz >= nw ? gz - nw : gz);
             const unsigned off = ((unsigned)gz * PS + (unsigned)gy * (unsigned)nx + (unsigned)gx) * SR;
 #pragma unroll
-            for (int k = 0; k < 5; ++k) s_p[k][c] = ld32<R>(arr(gp + (size_t)k * N, N), off);
+            for (int k = 0; k < 5; ++k) s_p[k][c] = ld32<R>(arr(gp + (size_t)k * QS, N), off);
         }
         __syncthreads();
     }
@@ -726,7 +727,7 @@ __device__ __forceinline__ void moments_imp_tile(const KParams &kp, const typena
     const unsigned n = (unsigned)p * PS + (unsigned)y * (unsigned)nx + (unsigned)x;
     S fr[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) fr[i] = ld32<S>(arr(f + (size_t)i * N, N), n * (unsigned)sizeof(S));
+    for (int i = 0; i < Q; ++i) fr[i] = ld32<S>(arr(f + (size_t)i * QS, N), n * (unsigned)sizeof(S));
     // FP16 storage: offsets decoded with the fields they were encoded with
     R rp = 0, pp = 0;
     if constexpr (PREC == P16) {
@@ -742,7 +743,7 @@ __device__ __forceinline__ void moments_imp_tile(const KParams &kp, const typena
         implicit_g<R>(get, walls && p == 1, walls && p == nw - 2, [&](int, R gv) { ph += gv; });
     } else {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) ph += dec_g<PREC, 3>(ld32<S>(arr(g + (size_t)i * N, N), n * (unsigned)sizeof(S)), i, pp);
+        for (int i = 0; i < Q; ++i) ph += dec_g<PREC, 3>(ld32<S>(arr(g + (size_t)i * QS, N), n * (unsigned)sizeof(S)), i, pp);
     }
     st32<R>(arr(rho, N), n * SR, r);
     st32<R>(arr(phi, N), n * SR, ph);
@@ -771,6 +772,7 @@ k_moments_imp(KParams kp, const typename Ty<PREC>::S *__restrict__ f, const type
     const int nx = kp.nx, ny = kp.ny, nw = kp.nw;
     const bool walls = kp.walls != 0;
     const unsigned N = (unsigned)kp.N, PS = (unsigned)kp.PS;
+    const unsigned QS = (unsigned)kp.QS;
     const int ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY, ntiles = ntx * nty;
     const unsigned b = xcd_block(blockIdx.x, gridDim.x);
     const int tile = (int)(b % (unsigned)ntiles), ch = (int)(b / (unsigned)ntiles);
@@ -793,7 +795,7 @@ k_moments_imp(KParams kp, const typename Ty<PREC>::S *__restrict__ f, const type
             const unsigned off = ((unsigned)pz * PS + (unsigned)gy * (unsigned)nx + (unsigned)gx) * SR;
             const R *gb = opaque(gp);
 #pragma unroll
-            for (int k = 0; k < 5; ++k) s_p[slot][k][c] = ld32<R>(arr(gb + (size_t)k * N, N), off);
+            for (int k = 0; k < 5; ++k) s_p[slot][k][c] = ld32<R>(arr(gb + (size_t)k * QS, N), off);
         }
     };
     const int lx = (int)threadIdx.x % TX, ly = (int)threadIdx.x / TX;
@@ -812,7 +814,7 @@ k_moments_imp(KParams kp, const typename Ty<PREC>::S *__restrict__ f, const type
         if (in) {
             const S *fb = opaque(f);
 #pragma unroll
-            for (int i = 0; i < Q; ++i) fr[i] = ld32<S>(arr(fb + (size_t)i * N, N), n * (unsigned)sizeof(S));
+            for (int i = 0; i < Q; ++i) fr[i] = ld32<S>(arr(fb + (size_t)i * QS, N), n * (unsigned)sizeof(S));
             // FP16 storage: offsets decoded with the density they were encoded with
             if constexpr (PREC == P16) rp = ld32<R>(arr(rprev, N), n * SR);
         }
@@ -859,6 +861,7 @@ __device__ __forceinline__ void implicit_g_global(const KParams &kp, const typen
     using R = typename Ty<PREC>::R;
     constexpr unsigned SR = sizeof(R);
     const unsigned N = (unsigned)kp.N, PS = (unsigned)kp.PS;
+    const unsigned QS = (unsigned)kp.QS;
     const int nx = kp.nx, ny = kp.ny, nw = kp.nw;
     const bool walls = kp.walls != 0;
     const int x = (int)(n % (unsigned)nx), y = (int)((n / (unsigned)nx) % (unsigned)ny), p = (int)(n / PS);
@@ -867,7 +870,7 @@ __device__ __forceinline__ void implicit_g_global(const KParams &kp, const typen
         const int sy = y - cy < 0 ? y - cy + ny : (y - cy >= ny ? y - cy - ny : y - cy);
         const int sz = walls ? p - cz : (p - cz < 0 ? p - cz + nw : (p - cz >= nw ? p - cz - nw : p - cz));
         const unsigned off = ((unsigned)sz * PS + (unsigned)sy * (unsigned)nx + (unsigned)sx) * SR;
-        return ld32<R>(arr(gp + (size_t)k * N, N), off);
+        return ld32<R>(arr(gp + (size_t)k * QS, N), off);
     };
     implicit_g<R>(get, walls && p == 1, walls && p == nw - 2, sink);
 }
@@ -885,12 +888,13 @@ k_g_materialize(KParams kp, const typename Ty<PREC>::R *__restrict__ gp, const t
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= count) return;
     const unsigned n = (unsigned)((kp.walls ? kp.PS : 0) + t), N = (unsigned)kp.N;
+    const unsigned QS = (unsigned)kp.QS;
     // FP16 storage: the rest population as an offset from the field phi the
     // next reader decodes it with (the current one)
     R pn = 0;
     if constexpr (PREC == P16) pn = ld32<R>(arr(pcur, N), n * (unsigned)sizeof(R));
     implicit_g_global<PREC>(kp, gp, n, [&](int i, R v) {
-        st32<S>(arr(g + (size_t)i * N, N), n * (unsigned)sizeof(S), enc_g<PREC, 3>(v, i, pn));
+        st32<S>(arr(g + (size_t)i * QS, N), n * (unsigned)sizeof(S), enc_g<PREC, 3>(v, i, pn));
     });
 }
 
@@ -1213,6 +1217,7 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
     const int tid = threadIdx.x;
     const int nx = kp.nx, ny = kp.ny, nw = kp.nw;
     const unsigned N = (unsigned)kp.N, PS = (unsigned)kp.PS;
+    const unsigned QS = (unsigned)kp.QS;
     const int ntx = (nx + TX - 1) / TX;
     const int x0 = (bx % ntx) * TX;
     const int y0 = (D == 3) ? (bx / ntx) * TY : 0;
@@ -1418,8 +1423,8 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
             const unsigned n = (unsigned)p * PS + nb[NIP / 2];
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
-                fr[i] = fin[(size_t)i * N + n];
-                if constexpr (PG) gr[i] = gin[(size_t)i * N + n];
+                fr[i] = fin[(size_t)i * QS + n];
+                if constexpr (PG) gr[i] = gin[(size_t)i * QS + n];
             }
         }
     };
@@ -1527,8 +1532,8 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
             }
             if constexpr (SPLIT) {
 #pragma unroll
-                for (int a = 0; a < D; ++a) fmu[(size_t)a * N + n] = F[a];
-                fmu[(size_t)D * N + n] = s_t[t0][NP][tcen];
+                for (int a = 0; a < D; ++a) fmu[(size_t)a * QS + n] = F[a];
+                fmu[(size_t)D * QS + n] = s_t[t0][NP][tcen];
             } else {
                 R rp = (R)0, pp = (R)0;
                 if constexpr (PREC == P16) { rp = rprev[n]; pp = pprev[n]; }
@@ -1555,7 +1560,7 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
                 R gg[Q];
 #pragma unroll
                 for (int i = 0; i < Q; ++i) {
-                    const S *gi = gin + (size_t)i * N;
+                    const S *gi = gin + (size_t)i * QS;
                     gg[i] = dec_g<PREC, D>(PG ? gr[PG ? i : 0] : gi[n], i, pp);
                 }
                 // stream f: push to x + c_i, halfway bounce-back at the walls
@@ -1564,13 +1569,13 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
                     const int cw = cdir(D, i, WA);
                     const int pt = p + cw;
                     if (walls && (pt < 1 || pt > nw - 2)) {
-                        S *fo = fout + (size_t)(Q - 1 - i) * N;
+                        S *fo = fout + (size_t)(Q - 1 - i) * QS;
                         put(&fo[n], enc_f<PREC, D>(f[i], Q - 1 - i, r0));
                     } else {
                         const int offf = cdir(D, i, 0) + (D == 3 ? cdir(D, i, 1) * FW : 0);
                         const int slf = cw < 0 ? sm : (cw > 0 ? sp : s0);
                         const unsigned nt = (unsigned)plane(pt) * PS + nbi(i);
-                        S *fo = fout + (size_t)i * N;
+                        S *fo = fout + (size_t)i * QS;
                         put(&fo[nt], enc_f<PREC, D>(f[i], i, s_r[slf][fcen + offf]));
                     }
                 }
@@ -1581,13 +1586,13 @@ fused_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ fin, cons
                     const int cw = cdir(D, i, WA);
                     const int pt = p + cw;
                     if (walls && (pt < 1 || pt > nw - 2)) {
-                        S *go = gout + (size_t)(Q - 1 - i) * N;
+                        S *go = gout + (size_t)(Q - 1 - i) * QS;
                         put(&go[n], enc_g<PREC, D>(gg[i], Q - 1 - i, p0));
                     } else {
                         const int offf = cdir(D, i, 0) + (D == 3 ? cdir(D, i, 1) * FW : 0);
                         const int slf = cw < 0 ? sm : (cw > 0 ? sp : s0);
                         const unsigned nt = (unsigned)plane(pt) * PS + nbi(i);
-                        S *go = gout + (size_t)i * N;
+                        S *go = gout + (size_t)i * QS;
                         put(&go[nt], enc_g<PREC, D>(gg[i], i, s_p[slf][fcen + offf]));
                     }
                 }
@@ -1706,6 +1711,7 @@ __device__ __forceinline__ void force_march3(const KParams &kp, const typename T
     const int tid = threadIdx.x;
     const int nx = kp.nx, ny = kp.ny, nw = kp.nw;
     const unsigned N = (unsigned)kp.N, PS = (unsigned)kp.PS;
+    const unsigned QS = (unsigned)kp.QS;
     const bool walls = kp.walls != 0;
     const int ntx = (nx + TX - 1) / TX;
     const int x0 = (bx % ntx) * TX, y0 = (bx / ntx) * TY;
@@ -1923,8 +1929,8 @@ __device__ __forceinline__ void force_march3(const KParams &kp, const typename T
             }
             const unsigned n = (unsigned)p * PS + own;
 #pragma unroll
-            for (int a = 0; a < 3; ++a) fmu[(size_t)a * N + n] = F[a];
-            fmu[(size_t)3 * N + n] = s_mu[o1];
+            for (int a = 0; a < 3; ++a) fmu[(size_t)a * QS + n] = F[a];
+            fmu[(size_t)3 * QS + n] = s_mu[o1];
         }
     }
 }
@@ -1988,6 +1994,7 @@ __device__ __forceinline__ int collide_node(const KParams &kp, const typename Ty
     constexpr unsigned SS = sizeof(S), SR = sizeof(R);
     const bool walls = kp.walls != 0;
     const unsigned N = (unsigned)kp.N, PS = (unsigned)kp.PS;
+    const unsigned QS = (unsigned)kp.QS;
     const int nx = kp.nx, ny = kp.ny, nw = kp.nw;
     const unsigned n = (unsigned)((walls ? kp.PS : 0) + t);
     const bool collide = !(kp.flags & 1u), alpha2 = (kp.flags & 2u) != 0;
@@ -1997,12 +2004,12 @@ __device__ __forceinline__ int collide_node(const KParams &kp, const typename Ty
 
     S fr[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) fr[i] = ld32<S>(arr(fin + (size_t)i * N, N), n * SS);
+    for (int i = 0; i < Q; ++i) fr[i] = ld32<S>(arr(fin + (size_t)i * QS, N), n * SS);
     const R r0 = ld32<R>(arr(rho, N), n * SR), p0 = ld32<R>(arr(phi, N), n * SR);
     R F[3] = {0, 0, 0};
 #pragma unroll
-    for (int a = 0; a < D; ++a) F[a] = ld32<R>(arr(fmu + (size_t)a * N, N), n * SR);
-    const R mup = ld32<R>(arr(fmu + (size_t)D * N, N), n * SR);
+    for (int a = 0; a < D; ++a) F[a] = ld32<R>(arr(fmu + (size_t)a * QS, N), n * SR);
+    const R mup = ld32<R>(arr(fmu + (size_t)D * QS, N), n * SR);
     R rp = (R)0, pp = (R)0;
     if constexpr (PREC == P16) { rp = ld32<R>(arr(rprev, N), n * SR); pp = ld32<R>(arr(pprev, N), n * SR); }
 
@@ -2056,18 +2063,18 @@ __device__ __forceinline__ int collide_node(const KParams &kp, const typename Ty
     if constexpr (GL != 0) {
         if (need_g) {
 #pragma unroll
-            for (int i = 0; i < Q; ++i) gg[i] = dec_g<PREC, D>(ld32<S>(arr(gin + (size_t)i * N, N), n * SS), i, pp);
+            for (int i = 0; i < Q; ++i) gg[i] = dec_g<PREC, D>(ld32<S>(arr(gin + (size_t)i * QS, N), n * SS), i, pp);
         }
     }
     // push streaming with halfway bounce-back at the walls
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         if (bounces(i)) {
-            st32<S>(arr(fout + (size_t)(Q - 1 - i) * N, N), n * SS, enc_f<PREC, D>(f[i], Q - 1 - i, r0));
+            st32<S>(arr(fout + (size_t)(Q - 1 - i) * QS, N), n * SS, enc_f<PREC, D>(f[i], Q - 1 - i, r0));
         } else {
             const unsigned nt = target(i);
             const R rt = PREC == P16 ? ld32<R>(arr(rho, N), nt / SS * SR) : r0;
-            st32<S>(arr(fout + (size_t)i * N, N), nt, enc_f<PREC, D>(f[i], i, rt));
+            st32<S>(arr(fout + (size_t)i * QS, N), nt, enc_f<PREC, D>(f[i], i, rt));
         }
     }
     if constexpr (GL == 3) {
@@ -2076,7 +2083,7 @@ __device__ __forceinline__ int collide_node(const KParams &kp, const typename Ty
         R *gp = (R *)gout;
         const R vals[5] = {geq_a<D, R>(v, p0, mup, Gam), p0, v[0], v[1], v[2]};
 #pragma unroll
-        for (int k = 0; k < 5; ++k) st32<R>(arr(gp + (size_t)k * N, N), n * SR, vals[k]);
+        for (int k = 0; k < 5; ++k) st32<R>(arr(gp + (size_t)k * QS, N), n * SR, vals[k]);
         return kind;
     }
     if (!need_g) {
@@ -2087,11 +2094,11 @@ __device__ __forceinline__ int collide_node(const KParams &kp, const typename Ty
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         if (bounces(i)) {
-            st32<S>(arr(gout + (size_t)(Q - 1 - i) * N, N), n * SS, enc_g<PREC, D>(gg[i], Q - 1 - i, p0));
+            st32<S>(arr(gout + (size_t)(Q - 1 - i) * QS, N), n * SS, enc_g<PREC, D>(gg[i], Q - 1 - i, p0));
         } else {
             const unsigned nt = target(i);
             const R pt = (PREC == P16 && i == Q / 2) ? ld32<R>(arr(phi, N), nt / SS * SR) : p0;
-            st32<S>(arr(gout + (size_t)i * N, N), nt, enc_g<PREC, D>(gg[i], i, pt));
+            st32<S>(arr(gout + (size_t)i * QS, N), nt, enc_g<PREC, D>(gg[i], i, pt));
         }
     }
     return kind;
@@ -2245,11 +2252,11 @@ k_init_pops(KParams kp, const typename Ty<PREC>::R *__restrict__ rho, const type
         if (i == Q / 2) continue;
         R gi = (R)wgt(D, i) * (R)3 * (R)kp.Gamma * mup;
         sum += gi;
-        g[(long long)i * kp.N + n] = enc_g<PREC, D>(gi, i, p0);
-        f[(long long)i * kp.N + n] = enc_f<PREC, D>((R)wgt(D, i) * r0, i, r0);
+        g[(long long)i * kp.QS + n] = enc_g<PREC, D>(gi, i, p0);
+        f[(long long)i * kp.QS + n] = enc_f<PREC, D>((R)wgt(D, i) * r0, i, r0);
     }
-    g[(long long)(Q / 2) * kp.N + n] = enc_g<PREC, D>(p0 - sum, Q / 2, p0);
-    f[(long long)(Q / 2) * kp.N + n] = enc_f<PREC, D>((R)wgt(D, Q / 2) * r0, Q / 2, r0);
+    g[(long long)(Q / 2) * kp.QS + n] = enc_g<PREC, D>(p0 - sum, Q / 2, p0);
+    f[(long long)(Q / 2) * kp.QS + n] = enc_f<PREC, D>((R)wgt(D, Q / 2) * r0, Q / 2, r0);
 }
 
 // ------------------------------------------------------------- observe ---
@@ -2279,9 +2286,9 @@ k_observe(KParams kp, const typename Ty<PREC>::S *__restrict__ f, const typename
         double r = 0, ph = 0, j[3] = {0, 0, 0};
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            double fi = (double)dec_f<PREC, D>(f[(long long)i * kp.N + n], i, rp);
+            double fi = (double)dec_f<PREC, D>(f[(long long)i * kp.QS + n], i, rp);
             r += fi;
-            ph += (double)dec_g<PREC, D>(g[(long long)i * kp.N + n], i, pp);
+            ph += (double)dec_g<PREC, D>(g[(long long)i * kp.QS + n], i, pp);
 #pragma unroll
             for (int a = 0; a < D; ++a)
                 if (cdir(D, i, a) != 0) j[a] += cdir(D, i, a) * fi;
@@ -2347,7 +2354,7 @@ k_reduce_sum(const double *__restrict__ partials, int nblocks, double *__restric
 
 template <int D, int PREC>
 __global__ void __launch_bounds__(256)
-k_export_pop(long long N, const typename Ty<PREC>::S *__restrict__ s, int i,
+k_export_pop(long long N, const typename Ty<PREC>::S *__restrict__ s /* population i */, int i,
              const typename Ty<PREC>::R *__restrict__ rprev, const typename Ty<PREC>::R *__restrict__ pprev,
              int isg, double *__restrict__ out)
 {
@@ -2356,8 +2363,7 @@ k_export_pop(long long N, const typename Ty<PREC>::S *__restrict__ s, int i,
     using R = typename Ty<PREC>::R;
     R rp = 0, pp = 0;
     if constexpr (PREC == P16) { rp = rprev[n]; pp = pprev[n]; }
-    out[n] = isg ? (double)dec_g<PREC, D>(s[(long long)i * N + n], i, pp)
-                 : (double)dec_f<PREC, D>(s[(long long)i * N + n], i, rp);
+    out[n] = isg ? (double)dec_g<PREC, D>(s[n], i, pp) : (double)dec_f<PREC, D>(s[n], i, rp);
 }
 
 template <typename R>
@@ -2842,7 +2848,7 @@ template <int D, int PREC>
 static int export_pop_t(const KParams &kp, const Buffers &b, int pc, int fc, int which, int i, hipStream_t st)
 {
     const void *src = which == 0 ? b.f[pc] : b.g[pc];
-    k_export_pop<D, PREC><<<nblk(kp.N, 256), 256, 0, st>>>(kp.N, (const typename Ty<PREC>::S *)src, i,
+    k_export_pop<D, PREC><<<nblk(kp.N, 256), 256, 0, st>>>(kp.N, (const typename Ty<PREC>::S *)src + (size_t)i * kp.QS, i,
                                                            (RP<PREC>)b.rho[fc], (RP<PREC>)b.phi[fc], which,
                                                            b.scratch);
     return LBM3_CHECK_LAUNCH();

@@ -47,6 +47,30 @@ def test_footprint_and_validation():
         assert L.lbm3_footprint(b) == 0
 
 
+def _align256(b):
+    return (b + 255) // 256 * 256
+
+
+@pytest.mark.parametrize("n, padded", [((256, 256, 256), True), ((200, 200, 200), False), ((96, 80, 50), False)])
+def test_footprint_uses_the_padded_array_stride(n, padded):
+    """Each array of a block (the 27 populations of a set, the force
+    components, the five g^eq values) and each field is QS nodes long: N
+    rounded up to 64, plus 544 when that is a multiple of 16384, so that the
+    arrays of a power-of-two grid do not start a multiple of 64 MiB apart.
+    The workspace of a D3Q27 FP32 simulation at tau_g = 1 (implicit g: one g
+    set) is then, region by region, f[2], g, rho[2], phi[2], F and mu_phi,
+    the five values, the N-double staging buffer, 64 counter slots, the
+    reduction partials and the 32 results."""
+    N = n[0] * n[1] * n[2]
+    qs = (N + 63) // 64 * 64
+    if qs % 16384 == 0:
+        qs += 544
+    assert (qs != N) == padded or (N % 64 != 0)
+    p = L.make_params(L.D3Q27, n, lam=(0.07, 0.03, 0.03), kap=(0.03, 0.03, 0.03), precision=L.FP32)
+    regions = [27 * qs * 4] * 3 + [qs * 4] * 4 + [4 * qs * 4, 5 * qs * 4, N * 8, 64 * 16 * 8, 1024 * 16 * 8, 32 * 8]
+    assert L.lbm3_footprint(p) == sum(_align256(b) for b in regions)
+
+
 def test_create_rejects_small_workspace_without_device():
     p = L.make_params(L.D2Q9, (16, 8), lam=(0.07, 0.03, 0.03), kap=(0.03, 0.03, 0.03))
     with pytest.raises(L.Lbm3Error) as e:
