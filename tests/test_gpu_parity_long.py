@@ -6,7 +6,7 @@ observables (momentum, kinetic energy, max |u|) and the 3D sphere fit; and
 a 16-request sample of the serving stream served by lbm3_server_* at 500
 steps.  Tolerances: FP64 max-abs C_k <= 1e-9 after 2000 steps; FP32 <= 1e-4
 where it holds (the 64^3 drop) and 5e-4 on the channel, the drop train and
-the served sample (their measured FP32 errors, 1.4e-4 to 3.2e-4, are stated
+the served sample (their measured FP32 errors, 1.4e-4 to 4.6e-4, are stated
 in the tests); FP16-offset storage <= 2e-3."""
 import numpy as np
 import pytest
@@ -37,8 +37,8 @@ def oracle_run(p, derived, init, steps):
     return o
 
 
-# FP32 errors after 2000 steps measured on configs 2 and 4 (2.2e-4 and
-# 3.2e-4, growing linearly in time: a slow drift of moving menisci and of the
+# FP32 errors after 2000 steps measured on configs 2 and 4 (2.3e-4 and
+# 4.6e-4, growing linearly in time: a slow drift of moving menisci and of the
 # gas density at contact lines, while an FP32 rounding of the initial fields
 # alone changes the FP64 run by 2e-8) exceed the 1e-4 asked for FP32; the
 # passing tests bound them at 5e-4 and the 1e-4 target is kept as an
@@ -66,7 +66,7 @@ def test_cfg2_full_size_2000_steps():
     """Config 2 (2048 x 64 capillary channel, liquid-2 slug x < 256, liquid-3
     films of 3 rows, geometric interpolation at 60 degrees) for 2000 steps:
     FP64 to 1e-9 and FP32 within 5e-4 against one oracle run (measured
-    3.2e-12 and 2.2e-4)."""
+    3.2e-12 and 2.3e-4)."""
     e64, e32 = cfg2_runs()
     assert e64 <= 1e-9
     assert e32 <= FP32_BOUND
@@ -109,11 +109,11 @@ def test_cfg4_cropped_2000_steps():
     """Config 4's recipe cropped to 1024 x 256 (the first five drops of the
     seeded train, alternating liquids, walls at theta21 45 / theta31 120 /
     theta23 90 degrees) for 2000 steps in FP32: max-abs C_k within 5e-4
-    (measured 3.2e-4, at contact lines in the first fluid layer)."""
+    (measured 4.6e-4, at contact lines in the first fluid layer)."""
     assert cfg4_run() <= FP32_BOUND
 
 
-@pytest.mark.xfail(reason="FP32 errors on configs 2 and 4 after 2000 steps measure 2.2e-4 and 3.2e-4 "
+@pytest.mark.xfail(reason="FP32 errors on configs 2 and 4 after 2000 steps measure 2.3e-4 and 4.6e-4 "
                           "(target 1e-4)", strict=False)
 def test_fp32_target_1e4_on_configs_2_and_4():
     """The FP32 target of 1e-4 after 2000 steps on configs 2 and 4 (config 1
