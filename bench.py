@@ -357,6 +357,9 @@ def main():
                          "kernel trace of the two")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 256 MiB device copy (HBM counter calibration) and exit")
+    ap.add_argument("--scale-grid", type=int, default=0, metavar="N",
+                    help="only run the 256^3 workload's recipe scaled to N^3 (FP32; sphere and film scaled) and "
+                         "print its step rate, kernel times, workspace and mass drift, then exit")
     ap.add_argument("--hbm-rate", action="store_true",
                     help="only time torch's own 2 GiB device copy and fill (an attainable HBM rate to set the "
                          "kernels' rates beside) and exit")
@@ -415,6 +418,29 @@ def main():
         tf = timed(lambda: y.fill_(2.0))
         print(json.dumps({"bytes": nb, "copy_ms": tc * 1e3, "copy_TBs": 2 * nb / tc / 1e12,
                           "fill_ms": tf * 1e3, "fill_TBs": nb / tf / 1e12}), flush=True)
+        return
+
+    if args.scale_grid:
+        n = (args.scale_grid,) * 3
+        fl = n[0] * n[1] * (n[2] - 2)
+        p = params3(L, L.FP32, n)
+        sim = L.Sim(p, device="cuda:0")
+        sim.init(*fields3(I, n))
+        o0 = sim.observe()
+        sim.step(args.warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        prof = sim.step_profiled(args.steps, SAMPLE_EVERY)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        o = sim.observe()
+        print(json.dumps({"grid": list(n), "fluid_nodes": fl, "precision": "fp32", "steps": args.steps,
+                          "warmup": args.warmup, "MLUPS": fl * args.steps / wall / 1e6,
+                          "ms_per_step": 1e3 * wall / args.steps,
+                          "kernel_ms_per_launch": {k: prof[k] for k in ("moments", "stencil", "collide", "ghost")},
+                          "workspace_bytes": L.lbm3_footprint(p), "n_bad": o["n_bad"], "status": o["status"],
+                          "mass_drift": [abs(o["mass"][k] - o0["mass"][k]) / max(abs(o0["mass"][k]), 1e-300)
+                                         for k in range(3)]}), flush=True)
         return
 
     precs = {"fp32": (L.FP32, 4, 4, False), "fp16s": (L.FP16S, 2, 4, True), "fp64": (L.FP64, 8, 8, False)}
