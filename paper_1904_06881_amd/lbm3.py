@@ -90,6 +90,11 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError("liblbm3.so not built: run __graft_entry__.build() or "
                               "python paper_1904_06881_amd/build.py")
+        # torch first: it ships its own HIP and HSA runtimes, and the library's
+        # HIP dependency must bind to the ones torch has loaded.  Loaded the
+        # other way round, the process holds two HSA runtimes and the
+        # library's sees no device.
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         vp, dp = C.c_void_p, C.POINTER(C.c_double)
         L.lbm3_footprint.restype = C.c_size_t
