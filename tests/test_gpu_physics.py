@@ -94,6 +94,41 @@ def test_laplace_liquid_liquid():
     assert abs(g16 - closed) < 0.05 * closed and abs(g32 - closed) < 0.05 * closed
 
 
+def laplace_3d(R, steps):
+    """A liquid-2 sphere of radius R in liquid 3, periodic D3Q27 box, FP64:
+    dP R / 2 (Laplace in 3D, dP = 2 gamma / R) with R from a sphere fit to the
+    C2 = 1/2 surface, and the closed form gamma_23."""
+    nb = 4 * R + 32
+    p = L.make_params(L.D3Q27, (nb, nb, nb), gamma=G, width=4.0, walls=False, precision=L.FP64)
+    s = L.Sim(p)
+    z, y, x = np.mgrid[0:nb, 0:nb, 0:nb].astype(np.float64)
+    c = nb / 2.0
+    sh = I.profile(R - np.sqrt((x - c) ** 2 + (y - c) ** 2 + (z - c) ** 2), 4.0)
+    s.init(*I.fields_from_conc(sh, 1.0 - sh))
+    s.step(steps)
+    r, ph = s.fields()
+    po = oracle_params(s, (nb, nb), walls=False)  # the bulk EOS and lambdas, as in 2D
+    lam = s.derived.lam
+    s.close()
+    m = nb // 2
+    dP = bulk_pressure(po, r[m, m, m], ph[m, m, m]) - bulk_pressure(po, r[2, 2, 2], ph[2, 2, 2])
+    C1, C2, C3 = O.concentrations(po, r, ph)
+    pts = O.contour_points_3d(C2)
+    Rf = O.kasa_fit_sphere(*[np.asarray(v) for v in pts])[3]
+    return dP * Rf / 2.0, (lam[1] + lam[2]) / 6.0, Rf
+
+
+def test_laplace_liquid_liquid_3d():
+    """A 2-3 sphere in D3Q27: dP R / 2 the same for R = 12 and 20 within 3 %,
+    and within 5 % of the closed-form gamma_23 (Eq. 38); measured 0.00976 and
+    0.00972 against 0.01 after 8000 steps."""
+    g12, closed, r12 = laplace_3d(12, 8000)
+    g20, _, r20 = laplace_3d(20, 8000)
+    say("3D dP R/2", g12, g20, "fitted radii", r12, r20, "closed form", closed)
+    assert abs(g12 - g20) < 0.03 * closed
+    assert abs(g12 - closed) < 0.05 * closed and abs(g20 - closed) < 0.05 * closed
+
+
 @pytest.mark.xfail(reason="curved liquid-gas interfaces carry an excess tension with the link-pressure "
                           "ideal force (dP R about 0.017-0.018 for gamma_12 = 0.01)", strict=False)
 def test_laplace_liquid_gas():
