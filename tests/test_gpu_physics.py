@@ -158,6 +158,21 @@ def sessile_angle(theta, liquid_liquid, steps):
     return O.contact_angle_2d(C2, exclude=8.0)[0]
 
 
+def sessile_angle_3d(precision, steps):
+    nx, ny, nz, R = 96, 96, 48, 24.0
+    p = L.make_params(L.D3Q27, (nx, ny, nz), gamma=G, width=4.0, theta_deg=(90.0, 90.0, 60.0), precision=precision)
+    s = L.Sim(p)
+    z, y, x = np.mgrid[0:nz, 0:ny, 0:nx].astype(np.float64)
+    sh = I.profile(R - np.sqrt((x - nx / 2) ** 2 + (y - ny / 2) ** 2 + (z - 0.5) ** 2), 4.0)
+    s.init(*I.fields_from_conc(sh, 1.0 - sh))
+    s.step(steps)
+    r, ph = s.fields()
+    po = oracle_params(s, (nx, ny))
+    s.close()
+    C1, C2, C3 = O.concentrations(po, r, ph)
+    return O.contact_angle_3d(C2, exclude=8.0)[0]
+
+
 def test_contact_angle_liquid_liquid_3d():
     """D3Q27, geometric interpolation through the planar three-point scheme
     (Eqs. 48-49): a liquid-2 hemisphere (R 24) in liquid 3 on a wall with
@@ -165,21 +180,14 @@ def test_contact_angle_liquid_liquid_3d():
     fit to the C2 = 1/2 surface above 8 nodes from the wall; 62.96 at 40000,
     63.00 at 60000).  The 2D drop settles at 61.6; the paper's bound is 1
     degree, tested here at 4.  (theta23 = 120 creeps to 103.6 by 60000 steps,
-    the obtuse-angle detection limit of the 2D case.)"""
-    nx, ny, nz, R = 96, 96, 48, 24.0
-    p = L.make_params(L.D3Q27, (nx, ny, nz), gamma=G, width=4.0, theta_deg=(90.0, 90.0, 60.0), precision=L.FP64)
-    s = L.Sim(p)
-    z, y, x = np.mgrid[0:nz, 0:ny, 0:nx].astype(np.float64)
-    sh = I.profile(R - np.sqrt((x - nx / 2) ** 2 + (y - ny / 2) ** 2 + (z - 0.5) ** 2), 4.0)
-    s.init(*I.fields_from_conc(sh, 1.0 - sh))
-    s.step(40000)
-    r, ph = s.fields()
-    po = oracle_params(s, (nx, ny))
-    s.close()
-    C1, C2, C3 = O.concentrations(po, r, ph)
-    a = O.contact_angle_3d(C2, exclude=8.0)[0]
-    say("3D theta_23 60 measured", a)
-    assert abs(a - 60.0) < 4.0
+    the obtuse-angle detection limit of the 2D case.)  The FP32 and
+    FP16-storage forms reach the FP64 angle within 1 degree."""
+    a64 = sessile_angle_3d(L.FP64, 40000)
+    a32 = sessile_angle_3d(L.FP32, 40000)
+    a16 = sessile_angle_3d(L.FP16S, 40000)
+    say("3D theta_23 60 measured: fp64", a64, "fp32", a32, "fp16 storage", a16)
+    assert abs(a64 - 60.0) < 4.0
+    assert abs(a32 - a64) < 1.0 and abs(a16 - a64) < 1.0
 
 
 @pytest.mark.parametrize("theta", [
