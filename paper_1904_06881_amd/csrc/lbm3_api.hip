@@ -691,7 +691,8 @@ static bool check_handles(lbm3 *const *hs, int n)
 
 // launches of the batch: moments per (D, precision), ghost layers per
 // (D, precision) where the step has them, fused (or stencil) per (tile
-// class, precision), collide per (D, precision) for two-kernel 3D steps
+// class, precision), collide per (D, precision, implicit g or not) for
+// two-kernel 3D steps
 static void plan(lbm3 *const *hs, int n, std::vector<Launch> &L)
 {
     auto find = [&](int kind, int D, int prec, int cls) -> Launch & {
@@ -725,7 +726,8 @@ static void plan(lbm3 *const *hs, int n, std::vector<Launch> &L)
         f.prefix.push_back(f.prefix.back() + (long long)fg.ntiles * fg.nchunks);
         long long cb = lbm3k::collide_blocks(k);
         if (cb > 0) {
-            Launch &c = find(3, k.D, prec, 0);
+            // simulations with implicit g apart from the others (class 1)
+            Launch &c = find(3, k.D, prec, hs[i]->b.gp ? 1 : 0);
             c.sims.push_back(i);
             c.prefix.push_back(c.prefix.back() + cb);
         }
@@ -812,7 +814,7 @@ lbm3_status enqueue(lbm3 *const *hs, int m, const Image &img, const void *dev_ba
             int r = l.kind == 0 ? lbm3k::launch_moments_batch(l.D, l.prec, d, tab, nb, phase, first, stream)
                   : l.kind == 1 ? lbm3k::launch_ghost_batch(l.D, l.prec, d, tab, nb, phase, stream)
                   : l.kind == 2 ? lbm3k::launch_fused_batch(l.cls, l.prec, d, tab, nb, phase, stream)
-                                : lbm3k::launch_collide_batch(l.D, l.prec, d, tab, nb, phase, stream);
+                                : lbm3k::launch_collide_batch(l.D, l.prec, l.cls == 1, d, tab, nb, phase, stream);
             if (r) return LBM3_EDEVICE;
         }
     }

@@ -146,7 +146,8 @@ int launch_ghost_batch(int D, int prec, const SimDesc *d, const int *sim, long l
                        void *stream);
 int launch_fused_batch(int cls, int prec, const SimDesc *d, const int *sim, long long nblocks, int phase,
                        void *stream);
-int launch_collide_batch(int D, int prec, const SimDesc *d, const int *sim, long long nblocks, int phase,
-                         void *stream);
+// implicit: every simulation of the table has implicit g (gp set)
+int launch_collide_batch(int D, int prec, bool implicit, const SimDesc *d, const int *sim, long long nblocks,
+                         int phase, void *stream);
 
 }  // namespace lbm3k

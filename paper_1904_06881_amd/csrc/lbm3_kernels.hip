@@ -2146,7 +2146,10 @@ k_collide(KParams kp, const typename Ty<PREC>::S *__restrict__ fin, const typena
                   (unsigned long long)s_cnt[threadIdx.x]);
 }
 
-template <int D, int PREC>
+// IMP: every simulation of the launch has implicit g (the batch groups them
+// apart), so only that form of the node is compiled in; the kernel holding
+// both forms needs registers for both and spills.
+template <int D, int PREC, bool IMP>
 __global__ void LBM3_COLLIDE_ATTR
 k_collide_batch(const SimDesc *__restrict__ d, const int *__restrict__ sim, int phase)
 {
@@ -2177,14 +2180,11 @@ k_collide_batch(const SimDesc *__restrict__ d, const int *__restrict__ sim, int 
     using G3 = std::integral_constant<int, 3>;
     if (t < count) {
         const bool uni = kp.PS % 64 == 0;
-        bool done = false;
-        if constexpr (D == 3) {
-            if (sd.gp) {
-                kind = uni ? node(std::true_type{}, G3{}) : node(std::false_type{}, G3{});
-                done = true;
-            }
+        if constexpr (IMP) {
+            kind = uni ? node(std::true_type{}, G3{}) : node(std::false_type{}, G3{});
+        } else {
+            kind = uni ? node(std::true_type{}, G2{}) : node(std::false_type{}, G2{});
         }
-        if (!done) kind = uni ? node(std::true_type{}, G2{}) : node(std::false_type{}, G2{});
     }
     count_kinds(kind, fast, s_cnt);
     __syncthreads();
@@ -2768,15 +2768,21 @@ int launch_fused_batch(int cls, int prec, const SimDesc *d, const int *sim, long
     return LBM3_CHECK_LAUNCH();
 }
 
-int launch_collide_batch(int D, int prec, const SimDesc *d, const int *sim, long long nblocks, int phase,
-                         void *stream)
+int launch_collide_batch(int D, int prec, bool implicit, const SimDesc *d, const int *sim, long long nblocks,
+                         int phase, void *stream)
 {
     if (nblocks <= 0 || D != 3) return nblocks <= 0 ? 0 : 1;
     hipStream_t st = (hipStream_t)stream;
     dim3 grid((unsigned)nblocks);
-    if (prec == P64) k_collide_batch<3, P64><<<grid, 256, 0, st>>>(d, sim, phase);
-    else if (prec == P32) k_collide_batch<3, P32><<<grid, 256, 0, st>>>(d, sim, phase);
-    else k_collide_batch<3, P16><<<grid, 256, 0, st>>>(d, sim, phase);
+    if (implicit) {
+        if (prec == P64) k_collide_batch<3, P64, true><<<grid, 256, 0, st>>>(d, sim, phase);
+        else if (prec == P32) k_collide_batch<3, P32, true><<<grid, 256, 0, st>>>(d, sim, phase);
+        else k_collide_batch<3, P16, true><<<grid, 256, 0, st>>>(d, sim, phase);
+    } else {
+        if (prec == P64) k_collide_batch<3, P64, false><<<grid, 256, 0, st>>>(d, sim, phase);
+        else if (prec == P32) k_collide_batch<3, P32, false><<<grid, 256, 0, st>>>(d, sim, phase);
+        else k_collide_batch<3, P16, false><<<grid, 256, 0, st>>>(d, sim, phase);
+    }
     return LBM3_CHECK_LAUNCH();
 }
 
