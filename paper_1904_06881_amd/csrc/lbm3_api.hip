@@ -774,6 +774,7 @@ lbm3_status build(lbm3 *const *hs, int n, Image &img)
         s.fmu = h->b.fmu;
         s.gp = h->b.gp;
         s.gimp0 = h->gimp ? 1 : 0;
+        s.mchunk = h->kp.D == 3 ? lbm3k::moments_march_chunk(h->kp) : 0;
         s.counters = h->b.counters;
         s.pc = h->pc;
         s.fc = h->fc;

@@ -89,6 +89,7 @@ struct SimDesc {
     int cblk0;                // and in the collide launch of the 3D two-kernel step
     void *gp;                 // implicit-g values (a, phi, v), or null
     int gimp0;                // g[pc] implicit (in gp) when the descriptors were written
+    int mchunk;               // planes per block of its moments march (moments_march_chunk)
 };
 
 // Fused launch geometry of one simulation: tile class (0: 2D 62-node tiles,
@@ -133,9 +134,11 @@ int observe_blocks(const KParams &kp);
 // belong to simulation sim[b] of the device descriptor array d.
 FusedGeom fused_geometry(const KParams &kp, int prec);
 long long moments_blocks(const KParams &kp, int prec);
-// the batched moments launch: the tiled pass for a simulation with an
+// the batched moments launch: the march for a simulation with an
 // implicit-g array (3D, tau_g = 1), else moments_blocks
 long long moments_batch_blocks(const KParams &kp, int prec, bool implicit);
+// planes per block of the moments march of a 3D simulation
+int moments_march_chunk(const KParams &kp);
 long long ghost_blocks(const KParams &kp);  // 0 when the step has no ghost launch
 long long collide_blocks(const KParams &kp);  // 0 unless the step is two-kernel
 // first: the first step since the descriptors were written (a simulation's

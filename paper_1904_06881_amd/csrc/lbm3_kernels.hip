@@ -673,108 +673,38 @@ __device__ __forceinline__ void implicit_g(Get get, bool low, bool high, Sink si
     }
 }
 
-// Moments pass of the implicit-g step: rho = sum of the stored f, phi = sum
-// of the delivered g (rebuilt as above), both in population order: the same
-// values and sums as the stored-g pass.  A block is a TX x TY tile of one
-// fluid plane (tile b of the simulation); the five values of the tile, its
-// one-node ring and the planes above and below go through LDS once (each is
-// read by 27 nodes).  imp false: g is stored (the first step after an
-// initialisation or an export), phi = sum of the stored g.
+// The implicit-g moments pass as a march: block b of a simulation takes the
+// TX x TY tile (b mod tiles) through the `chunk` consecutive fluid planes of
+// chunk (b / tiles), keeping the five values of three planes (tile and ring)
+// in an LDS ring, so that each plane is staged once per tile instead of
+// three times.  The same values and sums as the stored-g pass.  The buffer
+// resources of the 27 population arrays and the five value arrays are
+// rebuilt in every plane from bases the compiler cannot see through: held
+// across the loop, those 32 resources (128 scalar registers) spill into
+// vector lanes, and their reloads took a third of the loop's vector
+// instructions.  imp false (batched steps only): g is still stored (the
+// first step after an initialisation or an export), phi = the sum of the
+// stored g and nothing is staged.
 constexpr int kImpTX = 64, kImpTY = 4;
 template <int PREC, int TX, int TY>
-__device__ __forceinline__ void moments_imp_tile(const KParams &kp, const typename Ty<PREC>::S *__restrict__ f,
-                                                 const typename Ty<PREC>::S *__restrict__ g,
-                                                 const typename Ty<PREC>::R *__restrict__ gp,
-                                                 const typename Ty<PREC>::R *__restrict__ rprev,
-                                                 const typename Ty<PREC>::R *__restrict__ pprev,
-                                                 typename Ty<PREC>::R *__restrict__ rho,
-                                                 typename Ty<PREC>::R *__restrict__ phi, unsigned b, bool imp,
-                                                 typename Ty<PREC>::R (*s_p)[3 * (TY + 2) * (TX + 2)])
-{
-    using R = typename Ty<PREC>::R;
-    using S = typename Ty<PREC>::S;
-    constexpr int Q = 27, EX = TX + 2, EY = TY + 2, CELLS = 3 * EY * EX;
-    constexpr unsigned SR = sizeof(R);
-    const int nx = kp.nx, ny = kp.ny, nw = kp.nw;
-    const bool walls = kp.walls != 0;
-    const unsigned N = (unsigned)kp.N, PS = (unsigned)kp.PS;
-    const unsigned QS = (unsigned)kp.QS;
-    const int ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY;
-    const int tx = (int)(b % (unsigned)ntx), ty = (int)((b / (unsigned)ntx) % (unsigned)nty);
-    const int p = (int)(b / (unsigned)(ntx * nty)) + (walls ? 1 : 0);
-    const int x0 = tx * TX, y0 = ty * TY;
-    if (imp) {
-        for (int c = threadIdx.x; c < CELLS; c += TX * TY) {
-            const int lx = c % EX, ly = (c / EX) % EY, lz = c / (EX * EY);
-            // periodic wrap without a division (a tile may pass the end of a
-            // small grid more than once)
-            int gx = x0 + lx - 1, gy = y0 + ly - 1;
-            if (gx < 0) gx += nx;
-            while (gx >= nx) gx -= nx;
-            if (gy < 0) gy += ny;
-            while (gy >= ny) gy -= ny;
-            int gz = p + lz - 1;
-            if (!walls) gz = gz < 0 ? gz + nw : (gz >= nw ? gz - nw : gz);
-            const unsigned off = ((unsigned)gz * PS + (unsigned)gy * (unsigned)nx + (unsigned)gx) * SR;
-#pragma unroll
-            for (int k = 0; k < 5; ++k) s_p[k][c] = ld32<R>(arr(gp + (size_t)k * QS, N), off);
-        }
-        __syncthreads();
-    }
-    const int lx = (int)threadIdx.x % TX, ly = (int)threadIdx.x / TX;
-    const int x = x0 + lx, y = y0 + ly;
-    if (x >= nx || y >= ny) return;
-    const unsigned n = (unsigned)p * PS + (unsigned)y * (unsigned)nx + (unsigned)x;
-    S fr[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) fr[i] = ld32<S>(arr(f + (size_t)i * QS, N), n * (unsigned)sizeof(S));
-    // FP16 storage: offsets decoded with the fields they were encoded with
-    R rp = 0, pp = 0;
-    if constexpr (PREC == P16) {
-        rp = ld32<R>(arr(rprev, N), n * SR);
-        pp = ld32<R>(arr(pprev, N), n * SR);
-    }
-    R r = 0, ph = 0;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) r += dec_f<PREC, 3>(fr[i], i, rp);
-    if (imp) {
-        const int l0 = (EY + ly + 1) * EX + lx + 1;  // the node in the middle plane
-        auto get = [&](int cx, int cy, int cz, int k) { return s_p[k][l0 - cz * (EX * EY) - cy * EX - cx]; };
-        implicit_g<R>(get, walls && p == 1, walls && p == nw - 2, [&](int, R gv) { ph += gv; });
-    } else {
-#pragma unroll
-        for (int i = 0; i < Q; ++i) ph += dec_g<PREC, 3>(ld32<S>(arr(g + (size_t)i * QS, N), n * (unsigned)sizeof(S)), i, pp);
-    }
-    st32<R>(arr(rho, N), n * SR, r);
-    st32<R>(arr(phi, N), n * SR, ph);
-}
-
-// The single-simulation implicit-g moments pass as a march: a block takes a
-// TX x TY tile through `chunk` consecutive fluid planes, keeping the five
-// values of three planes (tile and ring) in an LDS ring, so that each plane
-// is staged once per tile instead of three times.  The same values and sums
-// as moments_imp_tile.  The buffer resources of the 27 population arrays and
-// the five value arrays are rebuilt in every plane from bases the compiler
-// cannot see through: held across the loop, those 32 resources (128 scalar
-// registers) spill into vector lanes, and their reloads took a third of the
-// loop's vector instructions.
-template <int PREC, int TX, int TY>
-__global__ void __launch_bounds__(TX * TY)
-k_moments_imp(KParams kp, const typename Ty<PREC>::S *__restrict__ f, const typename Ty<PREC>::R *__restrict__ gp,
-              const typename Ty<PREC>::R *__restrict__ rprev, typename Ty<PREC>::R *__restrict__ rho,
-              typename Ty<PREC>::R *__restrict__ phi, int chunk)
+__device__ __forceinline__ void moments_march(const KParams &kp, const typename Ty<PREC>::S *__restrict__ f,
+                                              const typename Ty<PREC>::S *__restrict__ g,
+                                              const typename Ty<PREC>::R *__restrict__ gp,
+                                              const typename Ty<PREC>::R *__restrict__ rprev,
+                                              const typename Ty<PREC>::R *__restrict__ pprev,
+                                              typename Ty<PREC>::R *__restrict__ rho,
+                                              typename Ty<PREC>::R *__restrict__ phi, int chunk, unsigned b, bool imp,
+                                              typename Ty<PREC>::R (*s_p)[5][(TY + 2) * (TX + 2)])
 {
     using R = typename Ty<PREC>::R;
     using S = typename Ty<PREC>::S;
     constexpr int Q = 27, EX = TX + 2, EY = TY + 2, CELLS = EY * EX;
-    constexpr unsigned SR = sizeof(R);
-    __shared__ R s_p[3][5][CELLS];
+    constexpr unsigned SR = sizeof(R), SS = sizeof(S);
     const int nx = kp.nx, ny = kp.ny, nw = kp.nw;
     const bool walls = kp.walls != 0;
     const unsigned N = (unsigned)kp.N, PS = (unsigned)kp.PS;
     const unsigned QS = (unsigned)kp.QS;
     const int ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY, ntiles = ntx * nty;
-    const unsigned b = xcd_block(blockIdx.x, gridDim.x);
     const int tile = (int)(b % (unsigned)ntiles), ch = (int)(b / (unsigned)ntiles);
     const int x0 = (tile % ntx) * TX, y0 = (tile / ntx) * TY;
     const int planes = walls ? nw - 2 : nw;
@@ -802,19 +732,21 @@ k_moments_imp(KParams kp, const typename Ty<PREC>::S *__restrict__ f, const type
     const int x = x0 + lx, y = y0 + ly;
     const bool in = x < nx && y < ny;
     const int l0 = (ly + 1) * EX + lx + 1;
-    stage(0, q0 + off0 - 1);
-    stage(1, q0 + off0);
+    if (imp) {
+        stage(0, q0 + off0 - 1);
+        stage(1, q0 + off0);
+    }
     for (int q = q0; q < q1; ++q) {
         const int pz = q + off0;
         const int sm = (q - q0) % 3, sc = (q - q0 + 1) % 3, sp = (q - q0 + 2) % 3;
-        stage(sp, pz + 1);
+        if (imp) stage(sp, pz + 1);
         const unsigned n = (unsigned)pz * PS + (unsigned)y * (unsigned)nx + (unsigned)x;
         S fr[Q];
         R rp = 0;
         if (in) {
             const S *fb = opaque(f);
 #pragma unroll
-            for (int i = 0; i < Q; ++i) fr[i] = ld32<S>(arr(fb + (size_t)i * QS, N), n * (unsigned)sizeof(S));
+            for (int i = 0; i < Q; ++i) fr[i] = ld32<S>(arr(fb + (size_t)i * QS, N), n * SS);
             // FP16 storage: offsets decoded with the density they were encoded with
             if constexpr (PREC == P16) rp = ld32<R>(arr(rprev, N), n * SR);
         }
@@ -823,17 +755,39 @@ k_moments_imp(KParams kp, const typename Ty<PREC>::S *__restrict__ f, const type
             R r = 0, ph = 0;
 #pragma unroll
             for (int i = 0; i < Q; ++i) r += dec_f<PREC, 3>(fr[i], i, rp);
-            // the source x - c lies in plane pz - cz: below (sm), this (sc) or above (sp)
-            auto get = [&](int cx, int cy, int cz, int k) {
-                const int sl = cz > 0 ? sm : (cz < 0 ? sp : sc);
-                return s_p[sl][k][l0 - cy * EX - cx];
-            };
-            implicit_g<R>(get, walls && pz == 1, walls && pz == nw - 2, [&](int, R gv) { ph += gv; });
+            if (imp) {
+                // the source x - c lies in plane pz - cz: below (sm), this (sc) or above (sp)
+                auto get = [&](int cx, int cy, int cz, int k) {
+                    const int sl = cz > 0 ? sm : (cz < 0 ? sp : sc);
+                    return s_p[sl][k][l0 - cy * EX - cx];
+                };
+                implicit_g<R>(get, walls && pz == 1, walls && pz == nw - 2, [&](int, R gv) { ph += gv; });
+            } else {
+                R pp = 0;
+                if constexpr (PREC == P16) pp = ld32<R>(arr(pprev, N), n * SR);
+                const S *gb = opaque(g);
+#pragma unroll
+                for (int i = 0; i < Q; ++i) ph += dec_g<PREC, 3>(ld32<S>(arr(gb + (size_t)i * QS, N), n * SS), i, pp);
+            }
             st32<R>(arr(rho, N), n * SR, r);
             st32<R>(arr(phi, N), n * SR, ph);
         }
         __syncthreads();
     }
+}
+
+// The single-simulation pass, its blocks renumbered so that each XCD takes a
+// contiguous range of tiles and chunks.
+template <int PREC, int TX, int TY>
+__global__ void __launch_bounds__(TX * TY)
+k_moments_imp(KParams kp, const typename Ty<PREC>::S *__restrict__ f, const typename Ty<PREC>::R *__restrict__ gp,
+              const typename Ty<PREC>::R *__restrict__ rprev, typename Ty<PREC>::R *__restrict__ rho,
+              typename Ty<PREC>::R *__restrict__ phi, int chunk)
+{
+    using R = typename Ty<PREC>::R;
+    __shared__ R s_p[3][5][(TY + 2) * (TX + 2)];
+    moments_march<PREC, TX, TY>(kp, f, nullptr, gp, rprev, nullptr, rho, phi, chunk,
+                                xcd_block(blockIdx.x, gridDim.x), true, s_p);
 }
 
 // planes per block of the marching moments pass: about 4096 blocks
@@ -846,11 +800,17 @@ inline int imp_chunk(const KParams &kp, long long ntiles)
     return (int)c;
 }
 
-// blocks of the tiled moments pass of one simulation
-inline long long imp_tiles(const KParams &kp)
+// planes per block and blocks of the march of one simulation
+int moments_march_chunk(const KParams &kp)
+{
+    return imp_chunk(kp, (long long)((kp.nx + kImpTX - 1) / kImpTX) * ((kp.ny + kImpTY - 1) / kImpTY));
+}
+static long long moments_march_blocks(const KParams &kp)
 {
     const long long planes = kp.walls ? kp.nw - 2 : kp.nw;
-    return (long long)((kp.nx + kImpTX - 1) / kImpTX) * ((kp.ny + kImpTY - 1) / kImpTY) * planes;
+    const long long ntiles = (long long)((kp.nx + kImpTX - 1) / kImpTX) * ((kp.ny + kImpTY - 1) / kImpTY);
+    const long long chunk = moments_march_chunk(kp);
+    return ntiles * ((planes + chunk - 1) / chunk);
 }
 
 // implicit_g at fluid node n with the values gathered from global memory
@@ -900,10 +860,11 @@ k_g_materialize(KParams kp, const typename Ty<PREC>::R *__restrict__ gp, const t
 
 // One launch over many simulations: block b belongs to simulation sim[b];
 // `phase` is the parity of the steps taken since the descriptors were
-// written, `first` whether this is the first of them.  A simulation whose g
-// is implicit (3D, tau_g = 1) rebuilds it from its five values per node,
-// gathered from global memory: one thread per node, the same values and
-// sums as the tiled single-simulation pass.
+// written, `first` whether this is the first of them.  A simulation with an
+// implicit-g array (3D, tau_g = 1) takes the march of the single-simulation
+// pass (blocks of 64 x 4 tiles and its descriptor's chunk of planes), with
+// g implicit or, at the first step, still stored; the others one thread per
+// node.
 template <int D, int PREC>
 __global__ void __launch_bounds__(256)
 k_moments_batch(const SimDesc *__restrict__ d, const int *__restrict__ sim, int phase, int first)
@@ -915,15 +876,15 @@ k_moments_batch(const SimDesc *__restrict__ d, const int *__restrict__ sim, int 
     const int pc = sd.pc ^ phase, fc = sd.fc ^ phase;
     const long long t = (long long)(blockIdx.x - sd.mblk0) * blockDim.x + threadIdx.x;
     if constexpr (D == 3) {
-        // simulations with an implicit-g array take the tiled pass (its
-        // block count, imp_tiles), their g implicit or still stored
-        __shared__ R s_p[5][3 * (kImpTY + 2) * (kImpTX + 2)];
+        // simulations with an implicit-g array take the march (its block
+        // count, moments_march_blocks), their g implicit or still stored
+        __shared__ R s_p[3][5][(kImpTY + 2) * (kImpTX + 2)];
         if (sd.gp) {
-            moments_imp_tile<PREC, kImpTX, kImpTY>(kp, on_global<const S>(d, sd.f[pc]), on_global<const S>(d, sd.g[pc]),
-                                                   on_global<const R>(d, sd.gp), on_global<const R>(d, sd.rho[fc]),
-                                                   on_global<const R>(d, sd.phi[fc]), on_global<R>(d, sd.rho[1 - fc]),
-                                                   on_global<R>(d, sd.phi[1 - fc]), blockIdx.x - sd.mblk0,
-                                                   !first || sd.gimp0, s_p);
+            moments_march<PREC, kImpTX, kImpTY>(kp, on_global<const S>(d, sd.f[pc]), on_global<const S>(d, sd.g[pc]),
+                                                on_global<const R>(d, sd.gp), on_global<const R>(d, sd.rho[fc]),
+                                                on_global<const R>(d, sd.phi[fc]), on_global<R>(d, sd.rho[1 - fc]),
+                                                on_global<R>(d, sd.phi[1 - fc]), sd.mchunk, blockIdx.x - sd.mblk0,
+                                                !first || sd.gimp0, s_p);
             return;
         }
     }
@@ -2500,10 +2461,8 @@ template <int PREC>
 static void moments_imp_t(const KParams &kp, const Buffers &b, int pc, int fc, hipStream_t st)
 {
     constexpr int TX = kImpTX, TY = kImpTY;
-    const long long planes = kp.walls ? kp.nw - 2 : kp.nw;
-    const long long ntiles = (long long)((kp.nx + TX - 1) / TX) * ((kp.ny + TY - 1) / TY);
-    const int chunk = imp_chunk(kp, ntiles);
-    const long long nb = ntiles * ((planes + chunk - 1) / chunk);
+    const int chunk = moments_march_chunk(kp);
+    const long long nb = moments_march_blocks(kp);
     stage_launch(k_moments_imp<PREC, TX, TY>, dim3((unsigned)nb), dim3(TX * TY), st, true, true, kp,
                  (SP<PREC>)b.f[pc], (RP<PREC>)b.gp, (RP<PREC>)b.rho[fc], (RP<PREC>)b.rho[1 - fc],
                  (RP<PREC>)b.phi[1 - fc], chunk);
@@ -2690,7 +2649,7 @@ long long collide_blocks(const KParams &kp)
 // ------------------------------------------------------- batched launches
 long long moments_batch_blocks(const KParams &kp, int prec, bool implicit)
 {
-    return kp.D == 3 && implicit ? imp_tiles(kp) : moments_blocks(kp, prec);
+    return kp.D == 3 && implicit ? moments_march_blocks(kp) : moments_blocks(kp, prec);
 }
 
 long long moments_blocks(const KParams &kp, int prec)
