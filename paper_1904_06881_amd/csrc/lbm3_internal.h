@@ -65,10 +65,10 @@ inline long long array_stride(long long N)
 
 // Device buffers of one simulation, carved out of the caller's workspace.
 struct Buffers {
-    void *f[2], *g[2];           // populations [Q][N], storage type by precision
+    void *f[2], *g[2];           // populations [Q][QS], storage type by precision
     void *rho[2], *phi[2];       // fields [N], compute type
-    void *fmu;                   // 3D two-kernel step: F, mu_phi [D + 1][N], compute type
-    void *gp;                    // implicit-g step: (a, phi, v) of g^eq [5][N], compute type (FP32 with
+    void *fmu;                   // 3D two-kernel step: F, mu_phi [D + 1][QS], compute type
+    void *gp;                    // implicit-g step: (a, phi, v) of g^eq [5][QS], compute type (FP32 with
                                  // FP16 storage), or null
     double *scratch;             // N doubles (upload / export staging)
     unsigned long long *counters;// kCntSlots (+ per-block) slots of kCntStride: newton, shortcut, fallback

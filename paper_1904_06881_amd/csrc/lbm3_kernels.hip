@@ -1,24 +1,33 @@
 // HIP kernels (gfx950) of the ternary high-density-ratio free-energy LBM
 // with wetting walls (Bala et al., arXiv:1904.06881).
 //
-// Data layout in HBM: populations SoA [Q][N] (x fastest), two buffers per
-// set (push streaming writes the other one); fields rho, phi [N] in the
-// compute type, two buffers (the FP16 storage decodes with the previous
-// step's fields); in 3D F and mu_phi [D + 1][N].  A step is two launches in
-// 2D and four in 3D:
-//   k_moments  rho, phi of every fluid node from its populations;
-//   k_ghost    (3D) wall ghost layers of rho, phi;
-//   k_fused    per block an in-plane tile (x in 2D, x-y in 3D) marching along
-//              the wall axis: a 5-plane LDS ring of rho, phi with halo 3 (in
-//              2D the wall ghost layers are filled in the block), a 3-plane
-//              LDS ring of -P and mu_phi with halo 1, then force, entropic
-//              collision of f, LBGK of g and push streaming with halfway
-//              bounce-back for one plane at a time;
-//   k_stencil  (3D) the same march up to the force, writing F and mu_phi;
-//   k_collide  (3D) one thread per fluid node: the fused kernel's collision,
-//              LBGK and streaming (k_fused does all of it in 3D too when one
-//              kernel is asked for).
-// k_ghost also fills the ghost layers for initialisation and export.
+// Data layout in HBM: populations SoA [Q][QS] (x fastest; QS = array_stride
+// of the node count, the arrays padded apart), two buffers per set (push
+// streaming writes the other one); fields rho, phi in the compute type, two
+// buffers (the FP16 storage decodes with the previous step's fields); in 3D
+// F and mu_phi [D + 1][QS]; at tau_g = 1 in 3D the five values (a, phi, v)
+// of g^eq [5][QS] in place of a second g set.  A step is two launches in 2D
+// and four in 3D:
+//   k_moments      rho, phi of every fluid node from its populations (2D, or
+//                  3D with stored g);
+//   k_moments_imp  (3D, tau_g = 1) the same as a march of 64 x 4 tiles along
+//                  the wall axis, g rebuilt from the five values of each
+//                  source node staged through a 3-plane LDS ring;
+//   k_ghost        (3D) wall ghost layers of rho, phi;
+//   k_fused        per block an in-plane tile (x in 2D, x-y in 3D) marching
+//                  along the wall axis: a 5-plane LDS ring of rho, phi with
+//                  halo 3 (in 2D the wall ghost layers are filled in the
+//                  block), a 3-plane LDS ring of -P and mu_phi with halo 1,
+//                  then force, entropic collision of f, LBGK of g and push
+//                  streaming with halfway bounce-back for one plane at a time;
+//   k_stencil      (3D) the same march up to the force, writing F and mu_phi;
+//   k_collide      (3D) one thread per fluid node: the fused kernel's
+//                  collision and streaming, and LBGK of g or, at tau_g = 1,
+//                  the five values of g^eq (k_fused does all of it in 3D too
+//                  when one kernel is asked for).
+// The _batch variants run the same per-node arithmetic for many simulations
+// in one launch.  k_ghost also fills the ghost layers for initialisation and
+// export.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -1142,7 +1151,7 @@ __device__ __forceinline__ int wrapl(int v, int n)
 // in 3D the ghost-layer kernel runs in between.
 //
 // SPLIT: the stencil pass of the two-kernel step instead (3D): the same
-// march and force, then F and mu_phi go to fmu ([D + 1][N]) and the
+// march and force, then F and mu_phi go to fmu ([D + 1][QS]) and the
 // populations are left to k_collide.
 // ONE: every chunk is one plane (no march loop, so the compiler's counts of
 // memory operations in flight need not merge a loop's back edge).
@@ -1641,7 +1650,7 @@ template <typename R> __device__ __forceinline__ R df3(R m, R p) { return (R)0.5
 // registers, y and x through LDS, plus the ideal part as the lattice
 // divergence of the link pressure of sqrt(rho), and the first-fluid-layer
 // wall rule and force-method wall force of Sec. IV.  Writes F and mu_phi
-// ([D + 1][N]).
+// ([D + 1][QS]).
 template <int PREC, int TX, int TY>
 __device__ __forceinline__ void force_march3(const KParams &kp, const typename Ty<PREC>::R *__restrict__ rho,
                                              const typename Ty<PREC>::R *__restrict__ phi,
